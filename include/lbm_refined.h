@@ -1,0 +1,185 @@
+/*
+ * lbm_refined.h -- C ABI of the MI355X refined lattice Boltzmann library.
+ *
+ * The library advances a D3Q19 SRT lattice Boltzmann simulation on a 2:1
+ * balanced forest of octrees (Schornbaum & Ruede, "Massively parallel
+ * algorithms for the lattice Boltzmann method on non-uniform grids"):
+ *
+ *   - the domain is a periodic grid of R_x x R_y x R_z root blocks; a block
+ *     is split into 8 children of half its size; every block on every level
+ *     holds n^3 cells, so level interfaces coincide with block faces
+ *     (section 3.2, section 4);
+ *   - neighbouring blocks differ by at most one level, counting face, edge
+ *     and corner neighbours across the periodic wrap (section 2.3);
+ *   - level L has grid spacing dx_0 / 2^L and time step dt_0 / 2^L
+ *     (acoustic scaling) and relaxation rate
+ *     omega_L = 2 omega_0 / (2^(L+1) + (1 - 2^L) omega_0)
+ *     (section 2.3, eq. omega_scaling_0);
+ *   - one coarse time step is NonUniformTimeStep(0) of Algorithm 1: level
+ *     L+1 takes two substeps per step of level L; coarse PDFs are copied
+ *     homogeneously into the fine ghost layers (explosion, eq. ctof) and the
+ *     PDFs streaming from the fine ghost layers into a coarse cell are
+ *     replaced by the mean of its 8 children (coalescence, eq. ftoc)
+ *     (section 4, section 4.3, section 4.4).
+ *
+ * Conventions
+ *   - Every call returns an int status: LBM_OK (0) or a negative LBM_E_*
+ *     code.  No C++ exception or abort crosses the ABI.  lbm_last_error()
+ *     returns a message for the calling thread's last failure.
+ *   - All host arrays are owned by the caller and only read or written
+ *     during the call.  All device memory is owned by the forest handle and
+ *     released by lbm_destroy().
+ *   - Canonical cell order: level-major (0 .. max level); inside a level,
+ *     blocks sorted by the Morton (Z-order) index of their integer position
+ *     on that level (x in the lowest bit); inside a block x fastest:
+ *     local = i + n (j + n k).
+ *   - Lattice units: rho0 = 1, c = 1 on every level.
+ *   - A forest handle is used by one host thread at a time.  Device work is
+ *     enqueued on the stream given at creation (the null stream if none);
+ *     calls that return host data synchronize that stream.
+ */
+#ifndef LBM_REFINED_H
+#define LBM_REFINED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define LBM_OK            0
+#define LBM_E_INVALID    -1  /* null pointer, bad size, bad parameter          */
+#define LBM_E_COVER      -2  /* explicit leaves do not tile the domain once     */
+#define LBM_E_UNBALANCED -3  /* explicit leaves violate 2:1 and balance == 0    */
+#define LBM_E_OOM        -4  /* device allocation failed                        */
+#define LBM_E_HIP        -5  /* HIP runtime error (message has the HIP string)  */
+#define LBM_E_NONFINITE  -6  /* a reduction found NaN or Inf                    */
+#define LBM_E_STATE      -7  /* call out of order (e.g. step before omega set)  */
+
+/* ---- storage forms ------------------------------------------------------ */
+/* PDFs are stored shifted by the lattice weights, h_a = f_a - w_a, in every
+ * form; arithmetic is FP64 for LBM_F64 and FP32 for the other two.          */
+#define LBM_F64          0
+#define LBM_F32          1
+#define LBM_F16_SHIFTED  2
+
+/* ---- schedules ------------------------------------------------------------ */
+#define LBM_SCHED_GRAPH      0  /* whole coarse step captured as one hipGraph   */
+#define LBM_SCHED_DIRECT     1  /* one launch per level substep, no graph        */
+#define LBM_SCHED_PER_BLOCK  2  /* one launch per block per level substep: the
+                                   plain "for all blocks on level L" form of
+                                   Algorithm 1, kept as a comparator            */
+
+typedef struct lbm_forest lbm_forest;
+
+/* Refinement callback (section 3.3: user callbacks mark blocks for
+ * refinement).  Asked once for every leaf of level `level` < max_level at
+ * integer block position (x, y, z) of that level; nonzero = split it. */
+typedef int (*lbm_refine_fn)(int level, int x, int y, int z, void *user);
+
+typedef struct {
+  int root_blocks[3];     /* R_x, R_y, R_z >= 1                                 */
+  int cells_per_block;    /* n in {4, 8, 16, 32}                                 */
+  int max_level;          /* deepest level allowed, 0 .. 20                       */
+  const int32_t *leaves;  /* optional explicit leaf list [num_leaves][4] =
+                             (L, x, y, z); must tile the domain exactly once    */
+  int64_t num_leaves;
+  lbm_refine_fn refine;   /* used when leaves == NULL: roots are split level by
+                             level where refine() says so                      */
+  void *refine_user;
+  int balance;            /* 1: add splits until 2:1 holds (section 3.3);
+                             0: an unbalanced explicit leaf list is an error.
+                             Callback-built forests are always balanced.        */
+  int storage;            /* LBM_F64, LBM_F32 or LBM_F16_SHIFTED                 */
+  int device;             /* HIP device ordinal                                   */
+  void *stream;           /* hipStream_t (e.g. torch.cuda.current_stream()
+                             .cuda_stream) or NULL for the null stream         */
+} lbm_forest_desc;
+
+/* Build the balanced forest, its level tables and all device storage.
+ * Errors: LBM_E_INVALID, LBM_E_COVER, LBM_E_UNBALANCED, LBM_E_OOM, LBM_E_HIP. */
+int lbm_create_block_forest(const lbm_forest_desc *desc, lbm_forest **out);
+
+/* Host only, no device work: the balanced forest that
+ * lbm_create_block_forest would build from `desc`, as a canonical leaf list
+ * out[count][4] = (L, x, y, z).  With out == NULL only *count is set;
+ * otherwise capacity (in leaves) must be >= the count.  Same errors as
+ * lbm_create_block_forest apart from device errors. */
+int lbm_build_leaves(const lbm_forest_desc *desc, int32_t *out, int64_t capacity, int64_t *count);
+
+/* Host only: lbm_level_stats of the forest `desc` describes, without
+ * allocating it (sizes for planning device memory). */
+int lbm_plan_level_stats(const lbm_forest_desc *desc, int level, int64_t out[8]);
+
+/* Release all device memory and the handle.  NULL is accepted. */
+int lbm_destroy(lbm_forest *f);
+
+/* Levels, blocks and interior cells.  level == -1 sums over all levels. */
+int lbm_num_levels(const lbm_forest *f, int *num_levels);
+int lbm_num_blocks(const lbm_forest *f, int level, int64_t *num_blocks);
+int lbm_num_cells(const lbm_forest *f, int level, int64_t *num_cells);
+
+/* Leaves in canonical order, out[num_blocks(-1)][4] = (L, x, y, z). */
+int lbm_get_leaves(const lbm_forest *f, int32_t *out);
+
+/* Per-level layout figures, out[8] = { real blocks, ghost blocks, interior
+ * cells, halo cells (the two streamed ghost layers), work tiles, coalesced
+ * (cell, direction) pairs, bytes per stored PDF, cells per block }. */
+int lbm_level_stats(const lbm_forest *f, int level, int64_t out[8]);
+
+/* Relaxation rates omega_L of all levels from omega_0 by eq. omega_scaling_0
+ * (section 2.3).  0 <= omega0 < 2; omega0 == 0 switches collision off
+ * (pure advection, a test mode).  Must be called before lbm_step_coarse. */
+int lbm_set_level_omega(lbm_forest *f, double omega0);
+int lbm_get_level_omega(const lbm_forest *f, int level, double *omega);
+
+/* f = f^eq(rho, u) (eq. fequ) on every interior cell.  rho[N], u[N][3],
+ * host FP64 in canonical order, N = lbm_num_cells(-1).  Synchronous. */
+int lbm_init_pdfs(lbm_forest *f, const double *rho, const double *u);
+
+/* Advance n_steps >= 0 coarse time steps (Algorithm 1 from level 0), with
+ * the schedule set by lbm_set_schedule.  Asynchronous on the stream. */
+int lbm_step_coarse(lbm_forest *f, int n_steps);
+
+/* Density and velocity of every interior cell (eq. fvelocity read as
+ * rho = sum f, u = sum e f / rho0), host FP64 in canonical order.
+ * Synchronizes the stream. */
+int lbm_get_moments(lbm_forest *f, double *rho, double *u);
+
+/* Volume-weighted mass and momentum, M = sum_L 8^-L sum_{cells} sum_a f_a
+ * and J = sum_L 8^-L sum sum e_a f_a, accumulated in FP64 on the device
+ * (cell volume (dx_L / dx_0)^3).  LBM_E_NONFINITE if NaN or Inf appears.
+ * Synchronizes the stream. */
+int lbm_mass(lbm_forest *f, double *mass, double momentum[3]);
+
+/* Schedule of lbm_step_coarse: LBM_SCHED_GRAPH (default), _DIRECT or
+ * _PER_BLOCK.  All three give bitwise identical results. */
+int lbm_set_schedule(lbm_forest *f, int schedule);
+
+/* Launch shape of the sweep kernel: persistent > 0 runs `persistent`
+ * workgroups per compute unit that loop over the level's work tiles;
+ * persistent == 0 launches one workgroup per tile.  Invalidates a captured
+ * graph.  Results do not depend on it. */
+int lbm_set_launch(lbm_forest *f, int persistent);
+
+/* Wait for all work enqueued by this forest. */
+int lbm_synchronize(lbm_forest *f);
+
+/* Raw shifted PDFs h = f - w of every interior cell, FP64, canonical order,
+ * layout [cell][19] with the direction order of lbm_lattice().  For exact
+ * checkpoint/resume (moments alone lose the non-equilibrium part). */
+int lbm_get_pdfs(lbm_forest *f, double *h);
+int lbm_set_pdfs(lbm_forest *f, const double *h);
+
+/* The D3Q19 velocity set used for raw PDF I/O: e[19][3], w[19]. */
+int lbm_lattice(int32_t *e, double *w);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_REFINED_H */

@@ -1,0 +1,666 @@
+// C ABI of the refined lattice Boltzmann library (declared in lbm_refined.h).
+//
+// Schedule of one coarse step (Algorithm 1 in post-collision form): the
+// finer level's two substeps run before every substep of a level, so the
+// launch list is the post-order of the level recursion,
+//   sweep(Lmax, 1), sweep(Lmax, 2), sweep(Lmax - 1, 1), ..., sweep(0, 1),
+// i.e. sum_L 2^L launches per coarse step.  Buffers: every level has A and
+// B; a level L > 0 reads A and writes B in its first substep and reads B,
+// writes A in its second, so after a parent step its state is in A again;
+// level 0 alternates A -> B, B -> A between coarse steps (two captured
+// graphs, one per parity).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm_refined.h"
+#include "forest.hpp"
+#include "kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      if (e_ == hipErrorOutOfMemory) return fail(LBM_E_OOM, "%s: %s", #expr, hipGetErrorString(e_)); \
+      return fail(LBM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));                        \
+    }                                                                                        \
+  } while (0)
+
+size_t storage_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
+
+struct LevelDev {
+  int64_t ncells = 0;  // interior cells
+  int nreal = 0, nghost = 0, nwork = 0;
+  void* A = nullptr;
+  void* B = nullptr;
+  int32_t* nbr = nullptr;
+  uint32_t* zmask = nullptr;
+  int32_t* parent = nullptr;
+  int32_t* child_ghost = nullptr;
+  uint32_t* flags = nullptr;
+  int32_t* work = nullptr;
+  double omega = 0.0;
+};
+
+struct Op {
+  int level;
+  SweepArgs args;
+};
+
+}  // namespace
+
+struct lbm_forest {
+  Forest forest;
+  std::vector<LevelTables> tabs;
+  std::vector<LevelDev> lv;
+  int storage = LBM_F32;
+  int n = 16;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int schedule = LBM_SCHED_GRAPH;
+  int persistent = 0;
+  int num_cu = 256;
+  bool omega_set = false;
+  int parity = 0;  // level 0 state in A (0) or B (1)
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int* d_err = nullptr;
+  double* d_partials = nullptr;
+  std::vector<void*> allocations;
+
+  ~lbm_forest() {
+    (void)hipSetDevice(device);
+    for (auto& g : graph)
+      if (g) (void)hipGraphExecDestroy(g);
+    for (void* p : allocations) (void)hipFree(p);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+template <typename T>
+int dev_alloc(lbm_forest* f, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return LBM_OK;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? LBM_E_OOM : LBM_E_HIP, "hipMalloc(%zu bytes): %s", count * sizeof(T),
+                hipGetErrorString(e));
+  }
+  f->allocations.push_back(q);
+  *p = static_cast<T*>(q);
+  return LBM_OK;
+}
+
+template <typename T>
+int upload(lbm_forest* f, T** p, const std::vector<T>& v) {
+  int rc = dev_alloc(f, p, v.size());
+  if (rc) return rc;
+  if (!v.empty()) HIP_TRY(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return LBM_OK;
+}
+
+void invalidate_graphs(lbm_forest* f) {
+  for (auto& g : f->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Post-order launch list of one coarse step for the given level-0 parity.
+void emit(const lbm_forest* f, int L, int substep, int parity, const void* parent_cur, std::vector<Op>& ops) {
+  const LevelDev& d = f->lv[L];
+  const void* cur;
+  void* nxt;
+  if (L == 0) {
+    cur = parity ? d.B : d.A;
+    nxt = parity ? d.A : d.B;
+  } else {
+    cur = substep == 1 ? d.A : d.B;
+    nxt = substep == 1 ? d.B : d.A;
+  }
+  const int nlev = int(f->lv.size());
+  if (L + 1 < nlev) {
+    emit(f, L + 1, 1, parity, cur, ops);
+    emit(f, L + 1, 2, parity, cur, ops);
+  }
+  Op op;
+  op.level = L;
+  SweepArgs& a = op.args;
+  a.cur = cur;
+  a.nxt = nxt;
+  a.par = parent_cur;
+  a.fine = L + 1 < nlev ? f->lv[L + 1].A : nullptr;
+  a.work = d.work;
+  a.nwork = d.nwork;
+  a.nreal = d.nreal;
+  a.nbr = d.nbr;
+  a.zmask = d.zmask;
+  a.parent = d.parent;
+  a.child_ghost = d.child_ghost;
+  a.flags = d.flags;
+  a.substep = substep;
+  a.omega = float(d.omega);
+  a.omega64 = d.omega;
+  a.err = f->d_err;
+  ops.push_back(op);
+}
+
+int grid_for(const lbm_forest* f, int nwork) {
+  if (f->persistent <= 0) return nwork;
+  return std::max(1, std::min(nwork, f->num_cu * f->persistent));
+}
+
+int run_ops(lbm_forest* f, const std::vector<Op>& ops, bool per_block) {
+  for (const Op& op : ops) {
+    if (op.args.nwork <= 0) continue;
+    if (!per_block) {
+      HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.args.nwork), f->stream));
+    } else {
+      const LevelTables& t = f->tabs[op.level];
+      const int nslot = t.nreal + t.nghost;
+      for (int s = 0; s < nslot; ++s) {
+        const int b = t.work_slot_begin[s], e = t.work_slot_begin[s + 1];
+        if (e == b) continue;
+        SweepArgs a = op.args;
+        a.work = op.args.work + b;
+        a.nwork = e - b;
+        HIP_TRY(launch_sweep(f->storage, f->n, a, a.nwork, f->stream));
+      }
+    }
+  }
+  return LBM_OK;
+}
+
+int capture_graph(lbm_forest* f, int parity) {
+  std::vector<Op> ops;
+  emit(f, 0, 1, parity, nullptr, ops);
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(f->stream, hipStreamCaptureModeThreadLocal));
+  int rc = run_ops(f, ops, false);
+  hipError_t e = hipStreamEndCapture(f->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(LBM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&f->graph[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(LBM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+int check_err_flag(lbm_forest* f) {
+  int h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, f->d_err, sizeof(int), hipMemcpyDeviceToHost, f->stream));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  if (h) return fail(LBM_E_STATE, "sweep table lookup failed (error bits 0x%x)", h);
+  return LBM_OK;
+}
+
+const void* current_buffer(const lbm_forest* f, int L) {
+  const LevelDev& d = f->lv[L];
+  return (L == 0 && f->parity) ? d.B : d.A;
+}
+
+void* current_buffer_mut(lbm_forest* f, int L) {
+  LevelDev& d = f->lv[L];
+  return (L == 0 && f->parity) ? d.B : d.A;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_lattice(int32_t* e, double* w) {
+  static const int E[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                               {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1},
+                               {1, 0, -1}, {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  if (!e || !w) return fail(LBM_E_INVALID, "null pointer");
+  for (int a = 0; a < 19; ++a) {
+    for (int d = 0; d < 3; ++d) e[3 * a + d] = E[a][d];
+    w[a] = a == 0 ? 1.0 / 3.0 : (a <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+  return LBM_OK;
+}
+
+static int validate_and_build(const lbm_forest_desc* d, Forest& forest, std::string& err) {
+  const int n = d->cells_per_block;
+  if (n != 4 && n != 8 && n != 16 && n != 32) {
+    err = "cells_per_block must be 4, 8, 16 or 32";
+    return LBM_E_INVALID;
+  }
+  for (int a = 0; a < 3; ++a)
+    if (d->root_blocks[a] < 1 || d->root_blocks[a] > 4096) {
+      err = "root_blocks out of range";
+      return LBM_E_INVALID;
+    }
+  if (d->max_level < 0 || d->max_level > 20) {
+    err = "max_level out of range";
+    return LBM_E_INVALID;
+  }
+  if (d->storage != LBM_F64 && d->storage != LBM_F32 && d->storage != LBM_F16_SHIFTED) {
+    err = "unknown storage form";
+    return LBM_E_INVALID;
+  }
+  if (!d->leaves && d->num_leaves) {
+    err = "num_leaves without leaves";
+    return LBM_E_INVALID;
+  }
+  int rc;
+  if (d->leaves) {
+    rc = forest.build_from_leaves(d->root_blocks, n, d->leaves, d->num_leaves, d->balance != 0, err);
+    if (rc == LBM_OK && forest.max_level > d->max_level) {
+      err = "leaf level above max_level";
+      return LBM_E_INVALID;
+    }
+    return rc;
+  }
+  return forest.build_from_callback(d->root_blocks, n, d->max_level, d->refine, d->refine_user, err);
+}
+
+int lbm_build_leaves(const lbm_forest_desc* d, int32_t* out, int64_t capacity, int64_t* count) {
+  if (!d || !count) return fail(LBM_E_INVALID, "null pointer");
+  Forest forest;
+  std::string err;
+  int rc = validate_and_build(d, forest, err);
+  if (rc) return fail(rc, "%s", err.c_str());
+  int64_t total = 0;
+  for (int L = 0; L < forest.num_levels(); ++L) total += int64_t(forest.level_leaves(L).size());
+  *count = total;
+  if (!out) return LBM_OK;
+  if (capacity < total) return fail(LBM_E_INVALID, "capacity %lld < %lld leaves", (long long)capacity, (long long)total);
+  size_t k = 0;
+  for (int L = 0; L < forest.num_levels(); ++L)
+    for (const Leaf& l : forest.level_leaves(L)) {
+      out[k++] = l.level;
+      out[k++] = l.x;
+      out[k++] = l.y;
+      out[k++] = l.z;
+    }
+  return LBM_OK;
+}
+
+static void fill_stats(const LevelTables& t, int storage, int n, int64_t out[8]) {
+  out[0] = t.nreal;
+  out[1] = t.nghost;
+  out[2] = int64_t(t.nreal) * n * n * n;
+  out[3] = t.halo_cells;
+  out[4] = int64_t(t.work.size());
+  out[5] = t.coalesced_pairs;
+  out[6] = int64_t(storage_bytes(storage));
+  out[7] = int64_t(n) * n * n;
+}
+
+int lbm_plan_level_stats(const lbm_forest_desc* d, int level, int64_t out[8]) {
+  if (!d || !out) return fail(LBM_E_INVALID, "null pointer");
+  Forest forest;
+  std::vector<LevelTables> tabs;
+  std::string err;
+  int rc = validate_and_build(d, forest, err);
+  if (rc) return fail(rc, "%s", err.c_str());
+  rc = build_level_tables(forest, tabs, err);
+  if (rc) return fail(rc, "%s", err.c_str());
+  if (level < 0 || level >= int(tabs.size())) return fail(LBM_E_INVALID, "level out of range");
+  fill_stats(tabs[level], d->storage, forest.n, out);
+  return LBM_OK;
+}
+
+int lbm_create_block_forest(const lbm_forest_desc* d, lbm_forest** out) {
+  if (!d || !out) return fail(LBM_E_INVALID, "null pointer");
+  *out = nullptr;
+  const int n = d->cells_per_block;
+  std::unique_ptr<lbm_forest> f(new (std::nothrow) lbm_forest());
+  if (!f) return fail(LBM_E_INVALID, "host allocation failed");
+  f->storage = d->storage;
+  f->n = n;
+  f->device = d->device;
+  std::string err;
+  int rc = validate_and_build(d, f->forest, err);
+  if (rc) return fail(rc, "%s", err.c_str());
+  rc = build_level_tables(f->forest, f->tabs, err);
+  if (rc) return fail(rc, "%s", err.c_str());
+
+  HIP_TRY(hipSetDevice(d->device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, d->device));
+  f->num_cu = prop.multiProcessorCount;
+  if (d->stream) {
+    f->stream = static_cast<hipStream_t>(d->stream);
+  } else {
+    // graph capture needs a stream other than the legacy null stream
+    HIP_TRY(hipStreamCreateWithFlags(&f->stream, hipStreamNonBlocking));
+    f->own_stream = true;
+  }
+
+  const size_t s = storage_bytes(f->storage);
+  const size_t n3 = size_t(n) * n * n;
+  f->lv.resize(f->tabs.size());
+  for (size_t L = 0; L < f->tabs.size(); ++L) {
+    const LevelTables& t = f->tabs[L];
+    LevelDev& v = f->lv[L];
+    v.nreal = t.nreal;
+    v.nghost = t.nghost;
+    v.nwork = int(t.work.size());
+    v.ncells = int64_t(t.nreal) * int64_t(n3);
+    const size_t bytes = size_t(t.nreal + t.nghost) * 19 * n3 * s;
+    uint8_t* A = nullptr;
+    uint8_t* B = nullptr;
+    if ((rc = dev_alloc(f.get(), &A, bytes))) return rc;
+    if ((rc = dev_alloc(f.get(), &B, bytes))) return rc;
+    if (bytes) {
+      HIP_TRY(hipMemset(A, 0, bytes));
+      HIP_TRY(hipMemset(B, 0, bytes));
+    }
+    v.A = A;
+    v.B = B;
+    if ((rc = upload(f.get(), &v.nbr, t.nbr))) return rc;
+    if ((rc = upload(f.get(), &v.zmask, t.zmask))) return rc;
+    if ((rc = upload(f.get(), &v.parent, t.parent))) return rc;
+    if ((rc = upload(f.get(), &v.child_ghost, t.child_ghost))) return rc;
+    if ((rc = upload(f.get(), &v.flags, t.flags))) return rc;
+    if ((rc = upload(f.get(), &v.work, t.work))) return rc;
+  }
+  if ((rc = dev_alloc(f.get(), &f->d_err, 1))) return rc;
+  HIP_TRY(hipMemset(f->d_err, 0, sizeof(int)));
+  if ((rc = dev_alloc(f.get(), &f->d_partials, size_t(kReduceGrid) * 5 * f->lv.size()))) return rc;
+  HIP_TRY(hipDeviceSynchronize());
+  *out = f.release();
+  g_err.clear();
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_forest* f) {
+  if (!f) return LBM_OK;
+  (void)hipSetDevice(f->device);
+  if (f->stream) (void)hipStreamSynchronize(f->stream);
+  delete f;
+  return LBM_OK;
+}
+
+int lbm_num_levels(const lbm_forest* f, int* num_levels) {
+  if (!f || !num_levels) return fail(LBM_E_INVALID, "null pointer");
+  *num_levels = int(f->lv.size());
+  return LBM_OK;
+}
+
+int lbm_num_blocks(const lbm_forest* f, int level, int64_t* num_blocks) {
+  if (!f || !num_blocks) return fail(LBM_E_INVALID, "null pointer");
+  if (level < -1 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
+  int64_t s = 0;
+  for (int L = 0; L < int(f->lv.size()); ++L)
+    if (level == -1 || level == L) s += f->lv[L].nreal;
+  *num_blocks = s;
+  return LBM_OK;
+}
+
+int lbm_num_cells(const lbm_forest* f, int level, int64_t* num_cells) {
+  if (!f || !num_cells) return fail(LBM_E_INVALID, "null pointer");
+  if (level < -1 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
+  int64_t s = 0;
+  for (int L = 0; L < int(f->lv.size()); ++L)
+    if (level == -1 || level == L) s += f->lv[L].ncells;
+  *num_cells = s;
+  return LBM_OK;
+}
+
+int lbm_get_leaves(const lbm_forest* f, int32_t* out) {
+  if (!f || !out) return fail(LBM_E_INVALID, "null pointer");
+  size_t k = 0;
+  for (int L = 0; L < f->forest.num_levels(); ++L)
+    for (const Leaf& l : f->forest.level_leaves(L)) {
+      out[k++] = l.level;
+      out[k++] = l.x;
+      out[k++] = l.y;
+      out[k++] = l.z;
+    }
+  return LBM_OK;
+}
+
+int lbm_level_stats(const lbm_forest* f, int level, int64_t out[8]) {
+  if (!f || !out) return fail(LBM_E_INVALID, "null pointer");
+  if (level < 0 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
+  fill_stats(f->tabs[level], f->storage, f->n, out);
+  return LBM_OK;
+}
+
+int lbm_set_level_omega(lbm_forest* f, double omega0) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  if (!(omega0 >= 0.0 && omega0 < 2.0)) return fail(LBM_E_INVALID, "omega0 must lie in [0, 2)");
+  for (size_t L = 0; L < f->lv.size(); ++L) {
+    const double p = std::ldexp(1.0, int(L));
+    f->lv[L].omega = 2.0 * omega0 / (2.0 * p + (1.0 - p) * omega0);  // eq. omega_scaling_0
+  }
+  f->omega_set = true;
+  invalidate_graphs(f);
+  return LBM_OK;
+}
+
+int lbm_get_level_omega(const lbm_forest* f, int level, double* omega) {
+  if (!f || !omega) return fail(LBM_E_INVALID, "null pointer");
+  if (level < 0 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
+  if (!f->omega_set) return fail(LBM_E_STATE, "omega not set");
+  *omega = f->lv[level].omega;
+  return LBM_OK;
+}
+
+int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
+  if (!f || !rho || !u) return fail(LBM_E_INVALID, "null pointer");
+  HIP_TRY(hipSetDevice(f->device));
+  int64_t total = 0;
+  lbm_num_cells(f, -1, &total);
+  double* d_rho = nullptr;
+  double* d_u = nullptr;
+  HIP_TRY(hipMalloc(&d_rho, std::max<int64_t>(total, 1) * sizeof(double)));
+  hipError_t e = hipMalloc(&d_u, std::max<int64_t>(total, 1) * 3 * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipFree(d_rho);
+    return fail(LBM_E_OOM, "hipMalloc: %s", hipGetErrorString(e));
+  }
+  int rc = LBM_OK;
+  auto body = [&]() -> int {
+    HIP_TRY(hipMemcpyAsync(d_rho, rho, total * sizeof(double), hipMemcpyHostToDevice, f->stream));
+    HIP_TRY(hipMemcpyAsync(d_u, u, total * 3 * sizeof(double), hipMemcpyHostToDevice, f->stream));
+    int64_t off = 0;
+    f->parity = 0;
+    for (size_t L = 0; L < f->lv.size(); ++L) {
+      const LevelDev& v = f->lv[L];
+      HIP_TRY(launch_init(f->storage, f->n, v.A, d_rho + off, d_u + 3 * off, v.ncells, f->stream));
+      off += v.ncells;
+    }
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    return LBM_OK;
+  };
+  rc = body();
+  (void)hipFree(d_rho);
+  (void)hipFree(d_u);
+  return rc;
+}
+
+int lbm_set_schedule(lbm_forest* f, int schedule) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  if (schedule != LBM_SCHED_GRAPH && schedule != LBM_SCHED_DIRECT && schedule != LBM_SCHED_PER_BLOCK)
+    return fail(LBM_E_INVALID, "unknown schedule");
+  f->schedule = schedule;
+  return LBM_OK;
+}
+
+int lbm_set_launch(lbm_forest* f, int persistent) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  if (persistent < 0 || persistent > 64) return fail(LBM_E_INVALID, "persistent must lie in [0, 64]");
+  f->persistent = persistent;
+  invalidate_graphs(f);
+  return LBM_OK;
+}
+
+int lbm_step_coarse(lbm_forest* f, int n_steps) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  if (n_steps < 0) return fail(LBM_E_INVALID, "n_steps < 0");
+  if (!f->omega_set) return fail(LBM_E_STATE, "lbm_set_level_omega must be called first");
+  HIP_TRY(hipSetDevice(f->device));
+  for (int s = 0; s < n_steps; ++s) {
+    const int p = f->parity;
+    if (f->schedule == LBM_SCHED_GRAPH) {
+      if (!f->graph[p]) {
+        int rc = capture_graph(f, p);
+        if (rc) return rc;
+      }
+      HIP_TRY(hipGraphLaunch(f->graph[p], f->stream));
+    } else {
+      std::vector<Op> ops;
+      emit(f, 0, 1, p, nullptr, ops);
+      int rc = run_ops(f, ops, f->schedule == LBM_SCHED_PER_BLOCK);
+      if (rc) return rc;
+    }
+    f->parity ^= 1;
+  }
+  return LBM_OK;
+}
+
+int lbm_synchronize(lbm_forest* f) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  HIP_TRY(hipSetDevice(f->device));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  return LBM_OK;
+}
+
+int lbm_get_moments(lbm_forest* f, double* rho, double* u) {
+  if (!f || !rho || !u) return fail(LBM_E_INVALID, "null pointer");
+  HIP_TRY(hipSetDevice(f->device));
+  int rc = check_err_flag(f);
+  if (rc) return rc;
+  int64_t off = 0;
+  for (size_t L = 0; L < f->lv.size(); ++L) {
+    const LevelDev& v = f->lv[L];
+    if (v.ncells == 0) continue;
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, v.ncells * 4 * sizeof(double)));
+    auto body = [&]() -> int {
+      HIP_TRY(launch_moments(f->storage, f->n, current_buffer(f, int(L)), d, d + v.ncells, v.ncells, f->stream));
+      HIP_TRY(hipMemcpyAsync(rho + off, d, v.ncells * sizeof(double), hipMemcpyDeviceToHost, f->stream));
+      HIP_TRY(hipMemcpyAsync(u + 3 * off, d + v.ncells, v.ncells * 3 * sizeof(double), hipMemcpyDeviceToHost,
+                             f->stream));
+      HIP_TRY(hipStreamSynchronize(f->stream));
+      return LBM_OK;
+    };
+    rc = body();
+    (void)hipFree(d);
+    if (rc) return rc;
+    off += v.ncells;
+  }
+  return LBM_OK;
+}
+
+int lbm_get_pdfs(lbm_forest* f, double* h) {
+  if (!f || !h) return fail(LBM_E_INVALID, "null pointer");
+  HIP_TRY(hipSetDevice(f->device));
+  int64_t off = 0;
+  for (size_t L = 0; L < f->lv.size(); ++L) {
+    const LevelDev& v = f->lv[L];
+    if (v.ncells == 0) continue;
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, v.ncells * 19 * sizeof(double)));
+    auto body = [&]() -> int {
+      HIP_TRY(launch_get_pdfs(f->storage, f->n, current_buffer(f, int(L)), d, v.ncells, f->stream));
+      HIP_TRY(hipMemcpyAsync(h + 19 * off, d, v.ncells * 19 * sizeof(double), hipMemcpyDeviceToHost, f->stream));
+      HIP_TRY(hipStreamSynchronize(f->stream));
+      return LBM_OK;
+    };
+    int rc = body();
+    (void)hipFree(d);
+    if (rc) return rc;
+    off += v.ncells;
+  }
+  return LBM_OK;
+}
+
+int lbm_set_pdfs(lbm_forest* f, const double* h) {
+  if (!f || !h) return fail(LBM_E_INVALID, "null pointer");
+  HIP_TRY(hipSetDevice(f->device));
+  int64_t off = 0;
+  for (size_t L = 0; L < f->lv.size(); ++L) {
+    const LevelDev& v = f->lv[L];
+    if (v.ncells == 0) continue;
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, v.ncells * 19 * sizeof(double)));
+    auto body = [&]() -> int {
+      HIP_TRY(hipMemcpyAsync(d, h + 19 * off, v.ncells * 19 * sizeof(double), hipMemcpyHostToDevice, f->stream));
+      HIP_TRY(launch_set_pdfs(f->storage, f->n, current_buffer_mut(f, int(L)), d, v.ncells, f->stream));
+      HIP_TRY(hipStreamSynchronize(f->stream));
+      return LBM_OK;
+    };
+    int rc = body();
+    (void)hipFree(d);
+    if (rc) return rc;
+    off += v.ncells;
+  }
+  return LBM_OK;
+}
+
+int lbm_mass(lbm_forest* f, double* mass, double momentum[3]) {
+  if (!f || !mass || !momentum) return fail(LBM_E_INVALID, "null pointer");
+  HIP_TRY(hipSetDevice(f->device));
+  int rc = check_err_flag(f);
+  if (rc) return rc;
+  const size_t nl = f->lv.size();
+  for (size_t L = 0; L < nl; ++L) {
+    if (f->lv[L].ncells == 0) continue;
+    HIP_TRY(launch_reduce(f->storage, f->n, current_buffer(f, int(L)), f->lv[L].ncells,
+                          f->d_partials + L * kReduceGrid * 5, f->stream));
+  }
+  std::vector<double> part(nl * kReduceGrid * 5, 0.0);
+  for (size_t L = 0; L < nl; ++L) {
+    if (f->lv[L].ncells == 0) continue;
+    HIP_TRY(hipMemcpyAsync(part.data() + L * kReduceGrid * 5, f->d_partials + L * kReduceGrid * 5,
+                           kReduceGrid * 5 * sizeof(double), hipMemcpyDeviceToHost, f->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  double M = 0, J[3] = {0, 0, 0}, bad = 0;
+  for (size_t L = 0; L < nl; ++L) {
+    if (f->lv[L].ncells == 0) continue;
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int b = 0; b < kReduceGrid; ++b)
+      for (int c = 0; c < 5; ++c) s[c] += part[(L * kReduceGrid + b) * 5 + c];
+    const double w = std::ldexp(1.0, -3 * int(L));  // cell volume (dx_L / dx_0)^3
+    M += w * (double(f->lv[L].ncells) + s[0]);      // sum_a f_a = 1 + sum_a h_a per cell
+    for (int c = 0; c < 3; ++c) J[c] += w * s[1 + c];
+    bad += s[4];
+  }
+  *mass = M;
+  for (int c = 0; c < 3; ++c) momentum[c] = J[c];
+  if (bad != 0 || !std::isfinite(M) || !std::isfinite(J[0]) || !std::isfinite(J[1]) || !std::isfinite(J[2]))
+    return fail(LBM_E_NONFINITE, "NaN or Inf in the PDFs");
+  return LBM_OK;
+}
+
+}  // extern "C"

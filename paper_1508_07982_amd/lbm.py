@@ -1,0 +1,276 @@
+"""Python binding of liblbm_refined.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts numpy
+arrays and Python callables to the C ABI declared in include/lbm_refined.h
+and raises LBMError on a negative status.  There is no fallback: if the
+library is not built, loading it raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "liblbm_refined.so")
+
+LBM_OK = 0
+ERRORS = {
+    -1: "LBM_E_INVALID", -2: "LBM_E_COVER", -3: "LBM_E_UNBALANCED", -4: "LBM_E_OOM",
+    -5: "LBM_E_HIP", -6: "LBM_E_NONFINITE", -7: "LBM_E_STATE",
+}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
+SCHEDULE = {"graph": 0, "direct": 1, "per_block": 2}
+
+REFINE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p)
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {message}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class ForestDesc(ctypes.Structure):
+    _fields_ = [
+        ("root_blocks", ctypes.c_int * 3),
+        ("cells_per_block", ctypes.c_int),
+        ("max_level", ctypes.c_int),
+        ("leaves", ctypes.POINTER(ctypes.c_int32)),
+        ("num_leaves", ctypes.c_int64),
+        ("refine", REFINE_FN),
+        ("refine_user", ctypes.c_void_p),
+        ("balance", ctypes.c_int),
+        ("storage", ctypes.c_int),
+        ("device", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+# (name, argtypes) of every exported entry point
+_SIGNATURES = {
+    "lbm_create_block_forest": [ctypes.POINTER(ForestDesc), ctypes.POINTER(ctypes.c_void_p)],
+    "lbm_destroy": [ctypes.c_void_p],
+    "lbm_num_levels": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
+    "lbm_num_blocks": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)],
+    "lbm_num_cells": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)],
+    "lbm_get_leaves": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_level_stats": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
+    "lbm_set_level_omega": [ctypes.c_void_p, ctypes.c_double],
+    "lbm_get_level_omega": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
+    "lbm_init_pdfs": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_step_coarse": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_get_moments": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_mass": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
+    "lbm_set_schedule": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_set_launch": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_synchronize": [ctypes.c_void_p],
+    "lbm_get_pdfs": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_set_pdfs": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_lattice": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_build_leaves": [ctypes.POINTER(ForestDesc), ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
+    "lbm_plan_level_stats": [ctypes.POINTER(ForestDesc), ctypes.c_int, ctypes.c_void_p],
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"HIP library missing at {path}; build it with `python -m paper_1508_07982_amd.build`")
+        lib = ctypes.CDLL(path)
+        for name, args in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib.lbm_last_error.argtypes = []
+        lib.lbm_last_error.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != LBM_OK:
+        msg = load_library().lbm_last_error().decode(errors="replace")
+        raise LBMError(rc, msg)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def lattice():
+    e = np.zeros((19, 3), dtype=np.int32)
+    w = np.zeros(19, dtype=np.float64)
+    _check(load_library().lbm_lattice(_ptr(e), _ptr(w)))
+    return e, w
+
+
+def _make_desc(roots, n, max_level, leaves, refine, balance, storage, device, stream):
+    d = ForestDesc()
+    roots = (roots,) * 3 if np.isscalar(roots) else tuple(roots)
+    for a in range(3):
+        d.root_blocks[a] = int(roots[a])
+    d.cells_per_block = int(n)
+    d.max_level = int(max_level)
+    keep = []
+    if leaves is not None:
+        arr = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
+        keep.append(arr)
+        d.leaves = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.num_leaves = len(arr)
+    if refine is not None:
+        cb = REFINE_FN(lambda L, x, y, z, user: int(bool(refine(L, x, y, z))))
+        keep.append(cb)
+        d.refine = cb
+    d.balance = int(bool(balance))
+    d.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    d.device = int(device)
+    d.stream = ctypes.c_void_p(int(stream)) if stream else None
+    return d, keep
+
+
+def build_leaves(roots, n, max_level, leaves=None, refine=None, balance=True) -> np.ndarray:
+    """Host-only: the library's balanced forest, canonical leaf list (N, 4)."""
+    d, keep = _make_desc(roots, n, max_level, leaves, refine, balance, "f32", 0, None)
+    count = ctypes.c_int64(0)
+    _check(load_library().lbm_build_leaves(ctypes.byref(d), None, 0, ctypes.byref(count)))
+    out = np.zeros((count.value, 4), dtype=np.int32)
+    _check(load_library().lbm_build_leaves(ctypes.byref(d), _ptr(out), count.value, ctypes.byref(count)))
+    del keep
+    return out
+
+
+def plan_level_stats(roots, n, max_level, level, leaves=None, refine=None, balance=True, storage="f32") -> dict:
+    """Host-only: layout figures of one level of the forest the library would build."""
+    d, keep = _make_desc(roots, n, max_level, leaves, refine, balance, storage, 0, None)
+    out = np.zeros(8, dtype=np.int64)
+    _check(load_library().lbm_plan_level_stats(ctypes.byref(d), int(level), _ptr(out)))
+    del keep
+    return _stats_dict(out)
+
+
+def _stats_dict(out):
+    keys = ("real_blocks", "ghost_blocks", "interior_cells", "halo_cells", "work_tiles", "coalesced_pairs",
+            "bytes_per_pdf", "cells_per_block")
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
+class Forest:
+    """A refined LBM simulation owned by the HIP library."""
+
+    def __init__(self, roots, n, max_level, leaves=None, refine=None, balance=True, storage="f32",
+                 device=0, stream=None):
+        self._lib = load_library()
+        self.storage = storage
+        self.n = int(n)
+        d, keep = _make_desc(roots, n, max_level, leaves, refine, balance, storage, device, stream)
+        h = ctypes.c_void_p()
+        _check(self._lib.lbm_create_block_forest(ctypes.byref(d), ctypes.byref(h)))
+        del keep
+        self._h = h
+        lv = ctypes.c_int()
+        _check(self._lib.lbm_num_levels(self._h, ctypes.byref(lv)))
+        self.num_levels = lv.value
+
+    # -- lifetime ---------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- sizes --------------------------------------------------------------------
+    def num_cells(self, level: int = -1) -> int:
+        v = ctypes.c_int64()
+        _check(self._lib.lbm_num_cells(self._h, int(level), ctypes.byref(v)))
+        return v.value
+
+    def num_blocks(self, level: int = -1) -> int:
+        v = ctypes.c_int64()
+        _check(self._lib.lbm_num_blocks(self._h, int(level), ctypes.byref(v)))
+        return v.value
+
+    def leaves(self) -> np.ndarray:
+        out = np.zeros((self.num_blocks(-1), 4), dtype=np.int32)
+        _check(self._lib.lbm_get_leaves(self._h, _ptr(out)))
+        return out
+
+    def level_stats(self, level: int) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        _check(self._lib.lbm_level_stats(self._h, int(level), _ptr(out)))
+        return _stats_dict(out)
+
+    def updates_per_coarse_step(self) -> int:
+        return sum((2 ** L) * self.num_cells(L) for L in range(self.num_levels))
+
+    # -- parameters and state --------------------------------------------------
+    def set_level_omega(self, omega0: float):
+        _check(self._lib.lbm_set_level_omega(self._h, float(omega0)))
+
+    def level_omega(self, level: int) -> float:
+        v = ctypes.c_double()
+        _check(self._lib.lbm_get_level_omega(self._h, int(level), ctypes.byref(v)))
+        return v.value
+
+    def set_schedule(self, schedule: str):
+        _check(self._lib.lbm_set_schedule(self._h, SCHEDULE[schedule]))
+
+    def set_launch(self, persistent: int):
+        _check(self._lib.lbm_set_launch(self._h, int(persistent)))
+
+    def init_pdfs(self, rho, u):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+        N = self.num_cells(-1)
+        if rho.shape != (N,) or u.shape != (N, 3):
+            raise ValueError(f"expected rho ({N},) and u ({N}, 3)")
+        _check(self._lib.lbm_init_pdfs(self._h, _ptr(rho), _ptr(u)))
+
+    def step_coarse(self, n_steps: int = 1):
+        _check(self._lib.lbm_step_coarse(self._h, int(n_steps)))
+
+    def synchronize(self):
+        _check(self._lib.lbm_synchronize(self._h))
+
+    def moments(self):
+        N = self.num_cells(-1)
+        rho = np.empty(N)
+        u = np.empty((N, 3))
+        _check(self._lib.lbm_get_moments(self._h, _ptr(rho), _ptr(u)))
+        return rho, u
+
+    def mass(self):
+        m = ctypes.c_double()
+        j = np.zeros(3)
+        _check(self._lib.lbm_mass(self._h, ctypes.byref(m), _ptr(j)))
+        return m.value, j
+
+    def get_pdfs(self) -> np.ndarray:
+        h = np.empty((self.num_cells(-1), 19))
+        _check(self._lib.lbm_get_pdfs(self._h, _ptr(h)))
+        return h
+
+    def set_pdfs(self, h):
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        if h.shape != (self.num_cells(-1), 19):
+            raise ValueError("expected (num_cells, 19)")
+        _check(self._lib.lbm_set_pdfs(self._h, _ptr(h)))
