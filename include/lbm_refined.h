@@ -123,9 +123,9 @@ int lbm_num_cells(const lbm_forest *f, int level, int64_t *num_cells);
 /* Leaves in canonical order, out[num_blocks(-1)][4] = (L, x, y, z). */
 int lbm_get_leaves(const lbm_forest *f, int32_t *out);
 
-/* Per-level layout figures, out[8] = { real blocks, ghost blocks, interior
- * cells, halo cells (the two streamed ghost layers), work tiles, coalesced
- * (cell, direction) pairs, bytes per stored PDF, cells per block }. */
+/* Per-level layout figures, out[8] = { blocks, blocks touching level L-1,
+ * interior cells, blocks touching level L+1, work tiles of the sweep,
+ * coalesced (cell, direction) pairs, bytes per stored PDF, cells per block }. */
 int lbm_level_stats(const lbm_forest *f, int level, int64_t out[8]);
 
 /* Relaxation rates omega_L of all levels from omega_0 by eq. omega_scaling_0

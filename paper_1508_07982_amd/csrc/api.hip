@@ -4,15 +4,19 @@
 // finer level's two substeps run before every substep of a level, so the
 // launch list is the post-order of the level recursion,
 //   sweep(Lmax, 1), sweep(Lmax, 2), sweep(Lmax - 1, 1), ..., sweep(0, 1),
-// i.e. sum_L 2^L launches per coarse step.  Buffers: every level has A and
-// B; a level L > 0 reads A and writes B in its first substep and reads B,
-// writes A in its second, so after a parent step its state is in A again;
-// level 0 alternates A -> B, B -> A between coarse steps (two captured
-// graphs, one per parity).
+// i.e. sum_L 2^L launches per coarse step.
+//
+// Buffers: level 0 alternates between two.  A level L >= 1 rotates through
+// three: with its state at the start of a parent step in buffer r, the first
+// substep writes r+1, the second reads r+1 and r and writes r+2 (mod 3); the
+// coarser level then reads r (state at t) and r+1 (state at t + 1/2) for the
+// coalescence.  The buffer assignment therefore repeats every 6 coarse steps;
+// one graph is captured per distinct assignment.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -54,14 +58,14 @@ size_t storage_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == 
 
 struct LevelDev {
   int64_t ncells = 0;  // interior cells
-  int nreal = 0, nghost = 0, nwork = 0;
-  void* A = nullptr;
-  void* B = nullptr;
+  uint64_t plane = 0;  // elements per direction plane: blocks * n^3
+  int nblocks = 0, nwork = 0, tiles_per_block = 0;
+  int nbuf = 0;
+  void* buf[3] = {nullptr, nullptr, nullptr};
   int32_t* nbr = nullptr;
-  uint32_t* zmask = nullptr;
-  int32_t* parent = nullptr;
-  int32_t* child_ghost = nullptr;
   uint32_t* flags = nullptr;
+  int32_t* fine_index = nullptr;
+  int32_t* fine_nbr = nullptr;
   int32_t* work = nullptr;
   double omega = 0.0;
 };
@@ -86,16 +90,15 @@ struct lbm_forest {
   int persistent = 0;
   int num_cu = 256;
   bool omega_set = false;
-  int parity = 0;  // level 0 state in A (0) or B (1)
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  std::vector<int> rot;  // per level: buffer holding the current state
+  std::map<std::vector<int>, hipGraphExec_t> graphs;
   int* d_err = nullptr;
   double* d_partials = nullptr;
   std::vector<void*> allocations;
 
   ~lbm_forest() {
     (void)hipSetDevice(device);
-    for (auto& g : graph)
-      if (g) (void)hipGraphExecDestroy(g);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     for (void* p : allocations) (void)hipFree(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
@@ -128,50 +131,67 @@ int upload(lbm_forest* f, T** p, const std::vector<T>& v) {
 }
 
 void invalidate_graphs(lbm_forest* f) {
-  for (auto& g : f->graph)
-    if (g) {
-      (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  for (auto& g : f->graphs) (void)hipGraphExecDestroy(g.second);
+  f->graphs.clear();
 }
 
-// Post-order launch list of one coarse step for the given level-0 parity.
-void emit(const lbm_forest* f, int L, int substep, int parity, const void* parent_cur, std::vector<Op>& ops) {
+// Post-order launch list: substep `substep` of level L, preceded by the two
+// substeps of level L+1.  `r` holds every level's current buffer and is
+// advanced as the launches are emitted.
+void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const void* parent_cur,
+          std::vector<Op>& ops) {
   const LevelDev& d = f->lv[L];
+  const int nlev = int(f->lv.size());
   const void* cur;
+  const void* prev = nullptr;
   void* nxt;
   if (L == 0) {
-    cur = parity ? d.B : d.A;
-    nxt = parity ? d.A : d.B;
+    cur = d.buf[r[0]];
+    nxt = d.buf[r[0] ^ 1];
+  } else if (substep == 1) {
+    cur = d.buf[r[L]];
+    nxt = d.buf[(r[L] + 1) % 3];
   } else {
-    cur = substep == 1 ? d.A : d.B;
-    nxt = substep == 1 ? d.B : d.A;
+    prev = d.buf[r[L]];
+    cur = d.buf[(r[L] + 1) % 3];
+    nxt = d.buf[(r[L] + 2) % 3];
   }
-  const int nlev = int(f->lv.size());
+  const void* fine0 = nullptr;
+  const void* fine1 = nullptr;
   if (L + 1 < nlev) {
-    emit(f, L + 1, 1, parity, cur, ops);
-    emit(f, L + 1, 2, parity, cur, ops);
+    const int rf = r[L + 1];
+    emit(f, L + 1, 1, r, cur, ops);
+    emit(f, L + 1, 2, r, cur, ops);
+    fine0 = f->lv[L + 1].buf[rf];
+    fine1 = f->lv[L + 1].buf[(rf + 1) % 3];
   }
   Op op;
   op.level = L;
   SweepArgs& a = op.args;
   a.cur = cur;
+  a.prev = prev;
   a.nxt = nxt;
   a.par = parent_cur;
-  a.fine = L + 1 < nlev ? f->lv[L + 1].A : nullptr;
+  a.fine0 = fine0;
+  a.fine1 = fine1;
+  a.plane = d.plane;
+  a.plane_par = L > 0 ? f->lv[L - 1].plane : 0;
+  a.plane_fine = L + 1 < nlev ? f->lv[L + 1].plane : 0;
   a.work = d.work;
   a.nwork = d.nwork;
-  a.nreal = d.nreal;
-  a.nbr = d.nbr;
-  a.zmask = d.zmask;
-  a.parent = d.parent;
-  a.child_ghost = d.child_ghost;
-  a.flags = d.flags;
   a.substep = substep;
+  a.nbr = d.nbr;
+  a.flags = d.flags;
+  a.fine_index = d.fine_index;
+  a.fine_nbr = d.fine_nbr;
   a.omega = float(d.omega);
   a.omega64 = d.omega;
   a.err = f->d_err;
   ops.push_back(op);
+  if (L == 0)
+    r[0] ^= 1;
+  else if (substep == 2)
+    r[L] = (r[L] + 2) % 3;
 }
 
 int grid_for(const lbm_forest* f, int nwork) {
@@ -185,14 +205,11 @@ int run_ops(lbm_forest* f, const std::vector<Op>& ops, bool per_block) {
     if (!per_block) {
       HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.args.nwork), f->stream));
     } else {
-      const LevelTables& t = f->tabs[op.level];
-      const int nslot = t.nreal + t.nghost;
-      for (int s = 0; s < nslot; ++s) {
-        const int b = t.work_slot_begin[s], e = t.work_slot_begin[s + 1];
-        if (e == b) continue;
+      const LevelDev& d = f->lv[op.level];
+      for (int s = 0; s < d.nblocks; ++s) {
         SweepArgs a = op.args;
-        a.work = op.args.work + b;
-        a.nwork = e - b;
+        a.work = op.args.work + size_t(s) * d.tiles_per_block;
+        a.nwork = d.tiles_per_block;
         HIP_TRY(launch_sweep(f->storage, f->n, a, a.nwork, f->stream));
       }
     }
@@ -200,9 +217,7 @@ int run_ops(lbm_forest* f, const std::vector<Op>& ops, bool per_block) {
   return LBM_OK;
 }
 
-int capture_graph(lbm_forest* f, int parity) {
-  std::vector<Op> ops;
-  emit(f, 0, 1, parity, nullptr, ops);
+int capture_graph(lbm_forest* f, const std::vector<Op>& ops, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(f->stream, hipStreamCaptureModeThreadLocal));
   int rc = run_ops(f, ops, false);
@@ -212,7 +227,7 @@ int capture_graph(lbm_forest* f, int parity) {
     return rc;
   }
   if (e != hipSuccess) return fail(LBM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&f->graph[parity], g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(LBM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
   return LBM_OK;
@@ -226,15 +241,9 @@ int check_err_flag(lbm_forest* f) {
   return LBM_OK;
 }
 
-const void* current_buffer(const lbm_forest* f, int L) {
-  const LevelDev& d = f->lv[L];
-  return (L == 0 && f->parity) ? d.B : d.A;
-}
+const void* current_buffer(const lbm_forest* f, int L) { return f->lv[L].buf[f->rot[L]]; }
 
-void* current_buffer_mut(lbm_forest* f, int L) {
-  LevelDev& d = f->lv[L];
-  return (L == 0 && f->parity) ? d.B : d.A;
-}
+void* current_buffer_mut(lbm_forest* f, int L) { return f->lv[L].buf[f->rot[L]]; }
 
 }  // namespace
 
@@ -312,10 +321,10 @@ int lbm_build_leaves(const lbm_forest_desc* d, int32_t* out, int64_t capacity, i
 }
 
 static void fill_stats(const LevelTables& t, int storage, int n, int64_t out[8]) {
-  out[0] = t.nreal;
-  out[1] = t.nghost;
-  out[2] = int64_t(t.nreal) * n * n * n;
-  out[3] = t.halo_cells;
+  out[0] = t.nblocks;
+  out[1] = t.coarse_blocks;
+  out[2] = int64_t(t.nblocks) * n * n * n;
+  out[3] = t.fine_blocks;
   out[4] = int64_t(t.work.size());
   out[5] = t.coalesced_pairs;
   out[6] = int64_t(storage_bytes(storage));
@@ -329,7 +338,7 @@ int lbm_plan_level_stats(const lbm_forest_desc* d, int level, int64_t out[8]) {
   std::string err;
   int rc = validate_and_build(d, forest, err);
   if (rc) return fail(rc, "%s", err.c_str());
-  rc = build_level_tables(forest, tabs, err);
+  rc = build_level_tables(forest, sweep_tile_cells(d->storage, d->cells_per_block), tabs, err);
   if (rc) return fail(rc, "%s", err.c_str());
   if (level < 0 || level >= int(tabs.size())) return fail(LBM_E_INVALID, "level out of range");
   fill_stats(tabs[level], d->storage, forest.n, out);
@@ -348,7 +357,7 @@ int lbm_create_block_forest(const lbm_forest_desc* d, lbm_forest** out) {
   std::string err;
   int rc = validate_and_build(d, f->forest, err);
   if (rc) return fail(rc, "%s", err.c_str());
-  rc = build_level_tables(f->forest, f->tabs, err);
+  rc = build_level_tables(f->forest, sweep_tile_cells(f->storage, f->n), f->tabs, err);
   if (rc) return fail(rc, "%s", err.c_str());
 
   HIP_TRY(hipSetDevice(d->device));
@@ -366,29 +375,30 @@ int lbm_create_block_forest(const lbm_forest_desc* d, lbm_forest** out) {
   const size_t s = storage_bytes(f->storage);
   const size_t n3 = size_t(n) * n * n;
   f->lv.resize(f->tabs.size());
+  f->rot.assign(f->tabs.size(), 0);
   for (size_t L = 0; L < f->tabs.size(); ++L) {
     const LevelTables& t = f->tabs[L];
     LevelDev& v = f->lv[L];
-    v.nreal = t.nreal;
-    v.nghost = t.nghost;
+    v.nblocks = t.nblocks;
     v.nwork = int(t.work.size());
-    v.ncells = int64_t(t.nreal) * int64_t(n3);
-    const size_t bytes = size_t(t.nreal + t.nghost) * 19 * n3 * s;
-    uint8_t* A = nullptr;
-    uint8_t* B = nullptr;
-    if ((rc = dev_alloc(f.get(), &A, bytes))) return rc;
-    if ((rc = dev_alloc(f.get(), &B, bytes))) return rc;
-    if (bytes) {
-      HIP_TRY(hipMemset(A, 0, bytes));
-      HIP_TRY(hipMemset(B, 0, bytes));
+    v.tiles_per_block = t.tiles_per_block;
+    v.ncells = int64_t(t.nblocks) * int64_t(n3);
+    v.plane = uint64_t(t.nblocks) * n3;
+    if (v.plane >= (uint64_t(1) << 32))
+      return fail(LBM_E_INVALID, "level %zu holds %llu cells; at most 2^32 - 1 per level are addressable", L,
+                  (unsigned long long)v.plane);
+    const size_t bytes = size_t(v.plane) * 19 * s;
+    v.nbuf = L == 0 ? 2 : 3;
+    for (int b = 0; b < v.nbuf; ++b) {
+      uint8_t* p = nullptr;
+      if ((rc = dev_alloc(f.get(), &p, bytes))) return rc;
+      if (bytes) HIP_TRY(hipMemset(p, 0, bytes));
+      v.buf[b] = p;
     }
-    v.A = A;
-    v.B = B;
     if ((rc = upload(f.get(), &v.nbr, t.nbr))) return rc;
-    if ((rc = upload(f.get(), &v.zmask, t.zmask))) return rc;
-    if ((rc = upload(f.get(), &v.parent, t.parent))) return rc;
-    if ((rc = upload(f.get(), &v.child_ghost, t.child_ghost))) return rc;
     if ((rc = upload(f.get(), &v.flags, t.flags))) return rc;
+    if ((rc = upload(f.get(), &v.fine_index, t.fine_index))) return rc;
+    if ((rc = upload(f.get(), &v.fine_nbr, t.fine_nbr))) return rc;
     if ((rc = upload(f.get(), &v.work, t.work))) return rc;
   }
   if ((rc = dev_alloc(f.get(), &f->d_err, 1))) return rc;
@@ -419,7 +429,7 @@ int lbm_num_blocks(const lbm_forest* f, int level, int64_t* num_blocks) {
   if (level < -1 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
   int64_t s = 0;
   for (int L = 0; L < int(f->lv.size()); ++L)
-    if (level == -1 || level == L) s += f->lv[L].nreal;
+    if (level == -1 || level == L) s += f->lv[L].nblocks;
   *num_blocks = s;
   return LBM_OK;
 }
@@ -492,10 +502,10 @@ int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
     HIP_TRY(hipMemcpyAsync(d_rho, rho, total * sizeof(double), hipMemcpyHostToDevice, f->stream));
     HIP_TRY(hipMemcpyAsync(d_u, u, total * 3 * sizeof(double), hipMemcpyHostToDevice, f->stream));
     int64_t off = 0;
-    f->parity = 0;
+    std::fill(f->rot.begin(), f->rot.end(), 0);
     for (size_t L = 0; L < f->lv.size(); ++L) {
       const LevelDev& v = f->lv[L];
-      HIP_TRY(launch_init(f->storage, f->n, v.A, d_rho + off, d_u + 3 * off, v.ncells, f->stream));
+      HIP_TRY(launch_init(f->storage, f->n, v.buf[0], v.plane, d_rho + off, d_u + 3 * off, v.ncells, f->stream));
       off += v.ncells;
     }
     HIP_TRY(hipStreamSynchronize(f->stream));
@@ -529,20 +539,23 @@ int lbm_step_coarse(lbm_forest* f, int n_steps) {
   if (!f->omega_set) return fail(LBM_E_STATE, "lbm_set_level_omega must be called first");
   HIP_TRY(hipSetDevice(f->device));
   for (int s = 0; s < n_steps; ++s) {
-    const int p = f->parity;
+    std::vector<int> r = f->rot;
+    std::vector<Op> ops;
+    emit(f, 0, 1, r, nullptr, ops);
     if (f->schedule == LBM_SCHED_GRAPH) {
-      if (!f->graph[p]) {
-        int rc = capture_graph(f, p);
+      auto it = f->graphs.find(f->rot);
+      if (it == f->graphs.end()) {
+        hipGraphExec_t g = nullptr;
+        int rc = capture_graph(f, ops, &g);
         if (rc) return rc;
+        it = f->graphs.emplace(f->rot, g).first;
       }
-      HIP_TRY(hipGraphLaunch(f->graph[p], f->stream));
+      HIP_TRY(hipGraphLaunch(it->second, f->stream));
     } else {
-      std::vector<Op> ops;
-      emit(f, 0, 1, p, nullptr, ops);
       int rc = run_ops(f, ops, f->schedule == LBM_SCHED_PER_BLOCK);
       if (rc) return rc;
     }
-    f->parity ^= 1;
+    f->rot = r;
   }
   return LBM_OK;
 }
@@ -566,7 +579,7 @@ int lbm_get_moments(lbm_forest* f, double* rho, double* u) {
     double* d = nullptr;
     HIP_TRY(hipMalloc(&d, v.ncells * 4 * sizeof(double)));
     auto body = [&]() -> int {
-      HIP_TRY(launch_moments(f->storage, f->n, current_buffer(f, int(L)), d, d + v.ncells, v.ncells, f->stream));
+      HIP_TRY(launch_moments(f->storage, f->n, current_buffer(f, int(L)), v.plane, d, d + v.ncells, v.ncells, f->stream));
       HIP_TRY(hipMemcpyAsync(rho + off, d, v.ncells * sizeof(double), hipMemcpyDeviceToHost, f->stream));
       HIP_TRY(hipMemcpyAsync(u + 3 * off, d + v.ncells, v.ncells * 3 * sizeof(double), hipMemcpyDeviceToHost,
                              f->stream));
@@ -591,7 +604,7 @@ int lbm_get_pdfs(lbm_forest* f, double* h) {
     double* d = nullptr;
     HIP_TRY(hipMalloc(&d, v.ncells * 19 * sizeof(double)));
     auto body = [&]() -> int {
-      HIP_TRY(launch_get_pdfs(f->storage, f->n, current_buffer(f, int(L)), d, v.ncells, f->stream));
+      HIP_TRY(launch_get_pdfs(f->storage, f->n, current_buffer(f, int(L)), v.plane, d, v.ncells, f->stream));
       HIP_TRY(hipMemcpyAsync(h + 19 * off, d, v.ncells * 19 * sizeof(double), hipMemcpyDeviceToHost, f->stream));
       HIP_TRY(hipStreamSynchronize(f->stream));
       return LBM_OK;
@@ -615,7 +628,7 @@ int lbm_set_pdfs(lbm_forest* f, const double* h) {
     HIP_TRY(hipMalloc(&d, v.ncells * 19 * sizeof(double)));
     auto body = [&]() -> int {
       HIP_TRY(hipMemcpyAsync(d, h + 19 * off, v.ncells * 19 * sizeof(double), hipMemcpyHostToDevice, f->stream));
-      HIP_TRY(launch_set_pdfs(f->storage, f->n, current_buffer_mut(f, int(L)), d, v.ncells, f->stream));
+      HIP_TRY(launch_set_pdfs(f->storage, f->n, current_buffer_mut(f, int(L)), v.plane, d, v.ncells, f->stream));
       HIP_TRY(hipStreamSynchronize(f->stream));
       return LBM_OK;
     };
@@ -635,7 +648,7 @@ int lbm_mass(lbm_forest* f, double* mass, double momentum[3]) {
   const size_t nl = f->lv.size();
   for (size_t L = 0; L < nl; ++L) {
     if (f->lv[L].ncells == 0) continue;
-    HIP_TRY(launch_reduce(f->storage, f->n, current_buffer(f, int(L)), f->lv[L].ncells,
+    HIP_TRY(launch_reduce(f->storage, f->n, current_buffer(f, int(L)), f->lv[L].plane, f->lv[L].ncells,
                           f->d_partials + L * kReduceGrid * 5, f->stream));
   }
   std::vector<double> part(nl * kReduceGrid * 5, 0.0);

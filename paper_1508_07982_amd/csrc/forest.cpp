@@ -209,195 +209,117 @@ int Forest::build_from_callback(const int R_[3], int n_, int max_level_, int (*r
 namespace {
 
 struct SlotMap {
-  std::unordered_map<uint64_t, int32_t> real, ghost;
+  std::unordered_map<uint64_t, int32_t> slot;
   int32_t find(int L, int x, int y, int z) const {
-    const uint64_t k = block_key(L, x, y, z);
-    auto it = real.find(k);
-    if (it != real.end()) return it->second;
-    auto g = ghost.find(k);
-    return g == ghost.end() ? kNbrNone : g->second;
+    auto it = slot.find(block_key(L, x, y, z));
+    return it == slot.end() ? -1 : it->second;
   }
 };
 
-// Live zones of a ghost block whose real neighbours are given by `real_dir`
-// (27 flags, offset index (dx+1) + 3 (dy+1) + 9 (dz+1)).
-uint32_t live_zones(const bool real_dir[27]) {
-  uint32_t mask = 0;
-  for (int zz = 0; zz < 3; ++zz)
-    for (int zy = 0; zy < 3; ++zy)
-      for (int zx = 0; zx < 3; ++zx) {
-        const int zone[3] = {zx, zy, zz};
-        bool live = false;
-        for (int d = 0; d < 27 && !live; ++d) {
-          if (d == kNbrSelf || !real_dir[d]) continue;
-          const int off[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
-          bool ok = true;
-          for (int a = 0; a < 3; ++a) {
-            if (off[a] == 0) continue;
-            if (off[a] == -1 && zone[a] != 0) ok = false;
-            if (off[a] == 1 && zone[a] != 2) ok = false;
-          }
-          live = ok;
-        }
-        if (live) mask |= 1u << (zx + 3 * zy + 9 * zz);
-      }
-  return mask;
-}
+const int kE[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                       {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1},
+                       {1, 0, -1}, {-1, 0, 1},  {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
 
 }  // namespace
 
-int build_level_tables(const Forest& f, std::vector<LevelTables>& out, std::string& err) {
+int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>& out, std::string& err) {
   const int n = f.n;
   const int n3 = n * n * n;
-  const int tile = std::min(256, n3);
+  if (tile_cells <= 0 || n3 % tile_cells) {
+    err = "tile size does not divide the block";
+    return LBM_E_INVALID;
+  }
   const int nlev = f.num_levels();
   out.assign(nlev, LevelTables{});
   std::vector<SlotMap> maps(nlev);
+  for (int L = 0; L < nlev; ++L) {
+    const auto& leaves = f.level_leaves(L);
+    for (int b = 0; b < int(leaves.size()); ++b)
+      maps[L].slot[block_key(L, leaves[b].x, leaves[b].y, leaves[b].z)] = b;
+  }
 
-  // pass 1: slots of every level
   for (int L = 0; L < nlev; ++L) {
     LevelTables& t = out[L];
+    const auto& leaves = f.level_leaves(L);
     t.level = L;
     t.n = n;
-    t.tile = tile;
-    t.tiles_per_block = n3 / tile;
-    const auto& leaves = f.level_leaves(L);
-    t.nreal = int(leaves.size());
-    for (int b = 0; b < t.nreal; ++b) maps[L].real[block_key(L, leaves[b].x, leaves[b].y, leaves[b].z)] = b;
-    std::vector<Leaf> ghosts;
-    if (L > 0) {
-      std::unordered_set<uint64_t> seen;
-      for (const Leaf& l : leaves)
-        for (int d = 0; d < 27; ++d) {
-          if (d == kNbrSelf) continue;
-          const int px = wrap(l.x + d % 3 - 1, f.dims(L, 0)), py = wrap(l.y + (d / 3) % 3 - 1, f.dims(L, 1)),
-                    pz = wrap(l.z + d / 9 - 1, f.dims(L, 2));
-          const int cl = f.covering_level(L, px, py, pz);
-          if (cl == L - 1) {
-            if (seen.insert(block_key(L, px, py, pz)).second) ghosts.push_back(Leaf{L, px, py, pz});
-          } else if (cl < L - 1) {
-            err = "2:1 balance violated";
-            return LBM_E_UNBALANCED;
-          }
-        }
-    }
-    std::sort(ghosts.begin(), ghosts.end(), [](const Leaf& a, const Leaf& b) {
-      return morton3(a.x, a.y, a.z) < morton3(b.x, b.y, b.z);
-    });
-    t.nghost = int(ghosts.size());
-    for (int g = 0; g < t.nghost; ++g) {
-      maps[L].ghost[block_key(L, ghosts[g].x, ghosts[g].y, ghosts[g].z)] = t.nreal + g;
-      t.ghost_pos.push_back(ghosts[g].x);
-      t.ghost_pos.push_back(ghosts[g].y);
-      t.ghost_pos.push_back(ghosts[g].z);
-    }
-  }
-
-  // pass 2: neighbour tables, zones, parents, children, work lists
-  for (int L = 0; L < nlev; ++L) {
-    LevelTables& t = out[L];
-    const int nslot = t.nreal + t.nghost;
-    t.nbr.assign(size_t(nslot) * 27, kNbrNone);
-    t.zmask.assign(nslot, 0);
-    t.parent.assign(nslot, -1);
-    t.flags.assign(nslot, 0);
-    t.child_ghost.assign(size_t(t.nreal) * 8, -1);
-    const auto& leaves = f.level_leaves(L);
-    for (int s = 0; s < nslot; ++s) {
-      const bool real = s < t.nreal;
-      int bx, by, bz;
-      if (real) {
-        bx = leaves[s].x, by = leaves[s].y, bz = leaves[s].z;
-      } else {
-        const int g = s - t.nreal;
-        bx = t.ghost_pos[3 * g], by = t.ghost_pos[3 * g + 1], bz = t.ghost_pos[3 * g + 2];
-      }
-      bool real_dir[27] = {};
-      uint32_t fl = real ? uint32_t(kReal) : 0u;
-      bool all_same = true;
+    t.tile = tile_cells;
+    t.tiles_per_block = n3 / tile_cells;
+    t.nblocks = int(leaves.size());
+    t.nbr.assign(size_t(t.nblocks) * 27, 0);
+    t.flags.assign(t.nblocks, 0);
+    t.fine_index.assign(t.nblocks, -1);
+    for (int s = 0; s < t.nblocks; ++s) {
+      const Leaf& l = leaves[s];
+      uint32_t fl = kAllSameLevel;
       for (int d = 0; d < 27; ++d) {
-        const int px = wrap(bx + d % 3 - 1, f.dims(L, 0)), py = wrap(by + (d / 3) % 3 - 1, f.dims(L, 1)),
-                  pz = wrap(bz + d / 9 - 1, f.dims(L, 2));
-        int32_t v = maps[L].find(L, px, py, pz);
-        if (v == kNbrNone && f.covering_level(L, px, py, pz) == L + 1) v = kNbrFine;
-        t.nbr[size_t(s) * 27 + d] = v;
-        real_dir[d] = v >= 0 && v < t.nreal;
-        if (d != kNbrSelf) {
-          if (!real_dir[d]) all_same = false;
-          if (v == kNbrFine) fl |= kHasFine;
-          if (v >= t.nreal) fl |= kHasGhost;
-          if (v == kNbrFine && !real) {
-            err = "ghost block touches the finer region";
+        const int px = wrap(l.x + d % 3 - 1, f.dims(L, 0)), py = wrap(l.y + (d / 3) % 3 - 1, f.dims(L, 1)),
+                  pz = wrap(l.z + d / 9 - 1, f.dims(L, 2));
+        const int cl = f.covering_level(L, px, py, pz);
+        int32_t v;
+        if (cl == L) {
+          v = maps[L].find(L, px, py, pz);
+        } else if (cl == L + 1) {
+          v = kNbrFine;
+          fl = (fl & ~uint32_t(kAllSameLevel)) | kHasFine;
+        } else if (cl == L - 1) {
+          const int32_t ps = maps[L - 1].find(L - 1, px >> 1, py >> 1, pz >> 1);
+          if (ps < 0) {
+            err = "coarse neighbour without a leaf";
             return LBM_E_UNBALANCED;
           }
-        }
-      }
-      if (real && all_same) fl |= kAllSameLevel;
-      t.flags[s] = fl;
-      t.zmask[s] = real ? 0x7FFFFFFu : live_zones(real_dir);
-      if (!real) {
-        const int32_t ps = maps[L - 1].find(L - 1, bx >> 1, by >> 1, bz >> 1);
-        if (ps < 0 || ps >= out[L - 1].nreal) {
-          err = "ghost block without a parent leaf";
+          v = kNbrCoarse0 - (ps * 8 + ((px & 1) | ((py & 1) << 1) | ((pz & 1) << 2)));
+          fl = (fl & ~uint32_t(kAllSameLevel)) | kHasCoarse;
+        } else {
+          err = "2:1 balance violated";
           return LBM_E_UNBALANCED;
         }
-        t.parent[s] = ps * 8 + ((bx & 1) | ((by & 1) << 1) | ((bz & 1) << 2));
-      } else if (L + 1 < nlev) {
-        for (int o = 0; o < 8; ++o) {
-          const uint64_t k = block_key(L + 1, 2 * bx + (o & 1), 2 * by + ((o >> 1) & 1), 2 * bz + (o >> 2));
-          auto g = maps[L + 1].ghost.find(k);
-          if (g != maps[L + 1].ghost.end()) t.child_ghost[size_t(s) * 8 + o] = g->second;
-        }
+        t.nbr[size_t(s) * 27 + d] = v;
       }
-    }
-
-    // work tiles: every tile of a real block; ghost tiles that hold a live cell
-    t.work.clear();
-    t.work_slot_begin.assign(nslot + 1, 0);
-    t.halo_cells = 0;
-    for (int s = 0; s < nslot; ++s) {
-      t.work_slot_begin[s] = int32_t(t.work.size());
-      for (int tl = 0; tl < t.tiles_per_block; ++tl) {
-        bool any = s < t.nreal;
-        for (int c = tl * tile; c < (tl + 1) * tile && s >= t.nreal; ++c) {
-          const int i = c % n, j = (c / n) % n, k = c / (n * n);
-          const int z = axis_zone(i, n) + 3 * axis_zone(j, n) + 9 * axis_zone(k, n);
-          if ((t.zmask[s] >> z) & 1u) {
-            any = true;
-            ++t.halo_cells;
+      t.flags[s] = fl;
+      t.coarse_blocks += (fl & kHasCoarse) ? 1 : 0;
+      if (fl & kHasFine) {
+        // neighbour tables of the 8 virtual level-(L+1) blocks of this block
+        const int row = t.fine_blocks++;
+        t.fine_index[s] = row;
+        t.fine_nbr.resize(size_t(row + 1) * 8 * 27, -1);
+        for (int o = 0; o < 8; ++o) {
+          const int vx = 2 * l.x + (o & 1), vy = 2 * l.y + ((o >> 1) & 1), vz = 2 * l.z + (o >> 2);
+          for (int d = 0; d < 27; ++d) {
+            const int px = wrap(vx + d % 3 - 1, f.dims(L + 1, 0)), py = wrap(vy + (d / 3) % 3 - 1, f.dims(L + 1, 1)),
+                      pz = wrap(vz + d / 9 - 1, f.dims(L + 1, 2));
+            t.fine_nbr[(size_t(row) * 8 + o) * 27 + d] = maps[L + 1].find(L + 1, px, py, pz);
           }
         }
-        if (any) t.work.push_back(s * t.tiles_per_block + tl);
       }
     }
-    t.work_slot_begin[nslot] = int32_t(t.work.size());
+    t.work.resize(size_t(t.nblocks) * t.tiles_per_block);
+    for (size_t w = 0; w < t.work.size(); ++w) t.work[w] = int32_t(w);
   }
 
-  // coalesced (cell, direction) pairs, for reporting only
-  static const int E[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
-                               {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1},
-                               {1, 0, -1}, {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  // coalesced (cell, direction) pairs, for reporting only: (X, a) is
+  // coalesced if X - e_a, or for an edge direction one of its two axis
+  // projections, lies in region(L+1)
   for (int L = 0; L + 1 < nlev; ++L) {
     LevelTables& t = out[L];
     int64_t pairs = 0;
-    for (int s = 0; s < t.nreal; ++s) {
+    for (int s = 0; s < t.nblocks; ++s) {
       if (!(t.flags[s] & kHasFine)) continue;
       for (int c = 0; c < n3; ++c) {
         const int ijk[3] = {c % n, (c / n) % n, c / (n * n)};
         for (int a = 1; a < 19; ++a) {
           int o[3];
           for (int ax = 0; ax < 3; ++ax) {
-            const int sc = ijk[ax] - E[a][ax];
+            const int sc = ijk[ax] - kE[a][ax];
             o[ax] = sc < 0 ? -1 : (sc >= n ? 1 : 0);
           }
           bool coal = false;
-          // the full source and, for edge directions, its two axis projections
           for (int mask = 1; mask < 8 && !coal; ++mask) {
             int d[3];
             bool valid = true;
             for (int ax = 0; ax < 3; ++ax) {
               d[ax] = (mask >> ax) & 1 ? o[ax] : 0;
-              if (((mask >> ax) & 1) && E[a][ax] == 0) valid = false;
+              if (((mask >> ax) & 1) && kE[a][ax] == 0) valid = false;
             }
             if (!valid) continue;
             const int di = (d[0] + 1) + 3 * (d[1] + 1) + 9 * (d[2] + 1);

@@ -4,14 +4,12 @@
 // callback or given as an explicit leaf list, 2:1 balance over face, edge
 // and corner neighbours.  Section 4: every block holds n^3 cells.
 //
-// Device-side view of one level L ("slots"):
-//   * real slots [0, nreal): the level-L leaves, canonical (Morton) order;
-//   * ghost slots [nreal, nslot): virtual level-L blocks inside level-(L-1)
-//     leaves that touch a level-L leaf (face, edge or corner).  Only their
-//     cells within Chebyshev distance 2 of a level-L leaf (the two innermost
-//     ghost layers, which are streamed but never collided, section 4) are
-//     computed; the rest of a ghost block is never written.
-// Each slot stores 19 x n^3 PDFs, slot-major: [slot][direction][cell].
+// Device-side view of one level L: slots [0, nblocks) are the level-L leaves
+// in canonical (Morton) order; a level buffer is direction-major,
+// [direction][slot][cell].  Nothing is stored for the fine ghost layers: the
+// two streamed halo layers of section 4 are reconstructed on the fly from
+// the level's state at the start of the parent step and from the parent
+// level (see kernels.hip).
 #pragma once
 
 #include <cstdint>
@@ -23,8 +21,10 @@
 namespace lbm {
 
 constexpr int kNbrSelf = 13;        // index of offset (0,0,0) in the 27-entry table
-constexpr int32_t kNbrNone = -1;    // no stored block there (never read by live cells)
 constexpr int32_t kNbrFine = -2;    // region of level L+1: values come by coalescence
+constexpr int32_t kNbrCoarse0 = -3; // region of level L-1: entry = kNbrCoarse0 - (pslot * 8 + octant),
+                                    // pslot = parent leaf's slot on level L-1, octant = the
+                                    // position of this virtual level-L block inside it
 
 struct Leaf {
   int level, x, y, z;
@@ -75,32 +75,27 @@ class Forest {
 struct LevelTables {
   int level = 0;
   int n = 0;
-  int nreal = 0, nghost = 0;
+  int nblocks = 0;
   int tiles_per_block = 0;     // n^3 / tile
-  int tile = 0;                // cells per work tile (= threads per workgroup)
-  std::vector<int32_t> nbr;           // [slot][27]
-  std::vector<uint32_t> zmask;        // [slot] live zones (27 bits)
-  std::vector<int32_t> parent;        // [slot] pslot * 8 + octant (ghost), -1 (real)
-  std::vector<int32_t> child_ghost;   // [real][8] ghost slot of level L+1 or -1
+  int tile = 0;                // cells per work tile (one workgroup of the sweep)
+  std::vector<int32_t> nbr;           // [slot][27]: slot, kNbrFine or a coarse code
   std::vector<uint32_t> flags;        // [slot]
+  std::vector<int32_t> fine_index;    // [slot]: row of fine_nbr, or -1 without a finer neighbour
+  std::vector<int32_t> fine_nbr;      // [row][octant][27]: level-(L+1) slot of the block at offset d
+                                      // from the virtual level-(L+1) block (2 b + octant), or -1
   std::vector<int32_t> work;          // slot * tiles_per_block + tile
-  std::vector<int32_t> work_slot_begin;  // [slot + 1] prefix into work (per-block launches)
-  std::vector<int32_t> ghost_pos;     // [ghost][3]
-  int64_t halo_cells = 0;
+  int64_t coarse_blocks = 0;          // blocks touching level L-1
+  int64_t fine_blocks = 0;            // blocks touching level L+1
   int64_t coalesced_pairs = 0;
 };
 
 enum SlotFlags : uint32_t {
-  kReal = 1u,           // collided interior block
-  kAllSameLevel = 2u,   // every neighbour is a real block of this level
-  kHasFine = 4u,        // some neighbour lies in region(L+1)
-  kHasGhost = 8u,       // some neighbour is a ghost block
+  kAllSameLevel = 1u,   // every neighbour is a level-L block
+  kHasFine = 2u,        // some neighbour lies in region(L+1)
+  kHasCoarse = 4u,      // some neighbour lies in region(L-1)
 };
 
-// Zone of local coordinate c along one axis: 0 = low two layers, 2 = high two
-// layers, 1 = in between; the zone index of a cell is zx + 3 zy + 9 zz.
-inline int axis_zone(int c, int n) { return c < 2 ? 0 : (c >= n - 2 ? 2 : 1); }
-
-int build_level_tables(const Forest& f, std::vector<LevelTables>& out, std::string& err);
+// tile_cells: cells per work tile of the sweep (a divisor of n^3).
+int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>& out, std::string& err);
 
 }  // namespace lbm

@@ -7,22 +7,27 @@
 
 namespace lbm {
 
-// Arguments of one level substep of the fused sweep.
+// Arguments of one level substep of the fused sweep.  PDF buffers are
+// direction-major: element (a, slot, cell) sits at a * plane + slot * n^3 + cell.
+// Levels L >= 1 keep three buffers: the state at the start of the parent
+// step (t), after the first substep (t + 1/2) and after the second (t + 1).
 struct SweepArgs {
-  const void* cur;            // level-L PDFs read by this substep  [slot][19][n^3]
-  void* nxt;                  // level-L PDFs written               [slot][19][n^3]
-  const void* par;            // level-(L-1) PDFs (post-collision) for the explosion gather
-  const void* fine;           // level-(L+1) PDFs after its two substeps, for coalescence
+  const void* cur;            // level-L state read by this substep (t or t + 1/2)
+  const void* prev;           // level-L state at t (second substep only)
+  void* nxt;                  // level-L state written
+  const void* par;            // level-(L-1) post-collision state (explosion source)
+  const void* fine0;          // level-(L+1) state at the start of its last parent step
+  const void* fine1;          // level-(L+1) state after the first of its two substeps
+  uint64_t plane;             // elements per direction of level L   (blocks * n^3)
+  uint64_t plane_par;         // same for level L-1
+  uint64_t plane_fine;        // same for level L+1
   const int32_t* work;        // work tiles: slot * tiles_per_block + tile
   int32_t nwork;
-  int32_t nreal;              // slots [0, nreal) are real blocks
+  int32_t substep;            // 1 or 2
   const int32_t* nbr;         // [slot][27]
-  const uint32_t* zmask;      // [slot]
-  const int32_t* parent;      // [slot]
-  const int32_t* child_ghost; // [real slot][8]
   const uint32_t* flags;      // [slot]
-  int32_t substep;            // 1: all non-interior sources come from the parent
-                              // 2: halo sources come from the level's own halo
+  const int32_t* fine_index;  // [slot]
+  const int32_t* fine_nbr;    // [row][8][27]
   float omega;                // omega_L (FP32 arithmetic forms)
   double omega64;             // omega_L (FP64 form)
   int* err;                   // error bits (table lookup failures)
@@ -30,24 +35,33 @@ struct SweepArgs {
 
 enum ErrBits : int { kErrNoSource = 1, kErrNoChild = 2 };
 
+// Cells per work tile of the sweep kernel (one workgroup's share).
+int sweep_tile_cells(int storage, int n);
+
 // storage: 0 = f64, 1 = f32, 2 = f16
 hipError_t launch_sweep(int storage, int n, const SweepArgs& a, int grid, hipStream_t stream);
 
-// h = f^eq(rho, u) - w on the interior cells [0, ncells) of one level.
-hipError_t launch_init(int storage, int n, void* buf, const double* rho, const double* u, int64_t ncells,
-                       hipStream_t stream);
+// The helpers below address the interior cells [0, ncells) of one level,
+// whose buffer has `plane` elements per direction.
 
-// rho = 1 + sum h, u = sum e h on the interior cells of one level.
-hipError_t launch_moments(int storage, int n, const void* buf, double* rho, double* u, int64_t ncells,
-                          hipStream_t stream);
+// h = f^eq(rho, u) - w.
+hipError_t launch_init(int storage, int n, void* buf, uint64_t plane, const double* rho, const double* u,
+                       int64_t ncells, hipStream_t stream);
 
-// Raw shifted PDFs of the interior cells, FP64 [cell][19].
-hipError_t launch_get_pdfs(int storage, int n, const void* buf, double* h, int64_t ncells, hipStream_t stream);
-hipError_t launch_set_pdfs(int storage, int n, void* buf, const double* h, int64_t ncells, hipStream_t stream);
+// rho = 1 + sum h, u = sum e h.
+hipError_t launch_moments(int storage, int n, const void* buf, uint64_t plane, double* rho, double* u,
+                          int64_t ncells, hipStream_t stream);
 
-// FP64 partial sums (sum h, sum e_x h, sum e_y h, sum e_z h, nonfinite count)
-// of the interior cells; `grid` workgroups write out[grid][5].
+// Raw shifted PDFs, FP64 [cell][19].
+hipError_t launch_get_pdfs(int storage, int n, const void* buf, uint64_t plane, double* h, int64_t ncells,
+                           hipStream_t stream);
+hipError_t launch_set_pdfs(int storage, int n, void* buf, uint64_t plane, const double* h, int64_t ncells,
+                           hipStream_t stream);
+
+// FP64 partial sums (sum h, sum e_x h, sum e_y h, sum e_z h, nonfinite count);
+// kReduceGrid workgroups write out[kReduceGrid][5].
 constexpr int kReduceGrid = 1024;
-hipError_t launch_reduce(int storage, int n, const void* buf, int64_t ncells, double* out, hipStream_t stream);
+hipError_t launch_reduce(int storage, int n, const void* buf, uint64_t plane, int64_t ncells, double* out,
+                         hipStream_t stream);
 
 }  // namespace lbm

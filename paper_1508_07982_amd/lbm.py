@@ -158,7 +158,7 @@ def plan_level_stats(roots, n, max_level, level, leaves=None, refine=None, balan
 
 
 def _stats_dict(out):
-    keys = ("real_blocks", "ghost_blocks", "interior_cells", "halo_cells", "work_tiles", "coalesced_pairs",
+    keys = ("blocks", "coarse_blocks", "interior_cells", "fine_blocks", "work_tiles", "coalesced_pairs",
             "bytes_per_pdf", "cells_per_block")
     return {k: int(v) for k, v in zip(keys, out)}
 
