@@ -163,6 +163,13 @@ int lbm_set_schedule(lbm_forest *f, int schedule);
  * graph.  Results do not depend on it. */
 int lbm_set_launch(lbm_forest *f, int persistent);
 
+/* Instrumented stepping: advance n_steps >= 1 coarse steps with direct
+ * launches, a hipEvent pair on the forest's stream around every sweep, and
+ * return the mean launch duration in milliseconds and the launch count per
+ * (level, substep): ms[L * 2 + s - 1], launches[L * 2 + s - 1] for
+ * L < num_levels, s in {1, 2} (level 0 only has s = 1).  Synchronizes. */
+int lbm_time_sweeps(lbm_forest *f, int n_steps, double *ms, int64_t *launches);
+
 /* Wait for all work enqueued by this forest. */
 int lbm_synchronize(lbm_forest *f);
 

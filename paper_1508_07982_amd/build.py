@@ -18,7 +18,7 @@ LIB = os.path.join(LIBDIR, "liblbm_refined.so")
 BUILD = os.path.join(ROOT, "_build")
 
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["forest.cpp", "kernels.hip", "api.hip"]
+SOURCES = ["forest.cpp", "kernels.hip", "sweep_f64.hip", "sweep_f32.hip", "sweep_f16.hip", "api.hip"]
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 ops are not emitted: some of their forms have given wrong
@@ -38,7 +38,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    objs, procs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD, src + ".o")
@@ -48,8 +48,11 @@ def build(verbose: bool = False) -> str:
             cmd = [hipcc()] + HIP_FLAGS + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((src, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [src for src, p in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError(f"compilation failed: {failed}")
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:

@@ -560,6 +560,56 @@ int lbm_step_coarse(lbm_forest* f, int n_steps) {
   return LBM_OK;
 }
 
+int lbm_time_sweeps(lbm_forest* f, int n_steps, double* ms, int64_t* launches) {
+  if (!f || !ms || !launches) return fail(LBM_E_INVALID, "null pointer");
+  if (n_steps < 1) return fail(LBM_E_INVALID, "n_steps < 1");
+  if (!f->omega_set) return fail(LBM_E_STATE, "lbm_set_level_omega must be called first");
+  HIP_TRY(hipSetDevice(f->device));
+  const size_t nl = f->lv.size();
+  std::vector<std::pair<size_t, hipEvent_t>> marks;  // (level * 2 + substep - 1, start event), end follows
+  std::vector<hipEvent_t> ends;
+  auto cleanup = [&]() {
+    for (auto& m : marks) (void)hipEventDestroy(m.second);
+    for (auto& e : ends) (void)hipEventDestroy(e);
+  };
+  auto body = [&]() -> int {
+    for (int s = 0; s < n_steps; ++s) {
+      std::vector<int> r = f->rot;
+      std::vector<Op> ops;
+      emit(f, 0, 1, r, nullptr, ops);
+      for (const Op& op : ops) {
+        if (op.args.nwork <= 0) continue;
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        marks.emplace_back(size_t(op.level) * 2 + size_t(op.args.substep - 1), e0);
+        HIP_TRY(hipEventCreate(&e1));
+        ends.push_back(e1);
+        HIP_TRY(hipEventRecord(e0, f->stream));
+        HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.args.nwork), f->stream));
+        HIP_TRY(hipEventRecord(e1, f->stream));
+      }
+      f->rot = r;
+    }
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    for (size_t i = 0; i < 2 * nl; ++i) {
+      ms[i] = 0.0;
+      launches[i] = 0;
+    }
+    for (size_t i = 0; i < marks.size(); ++i) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, marks[i].second, ends[i]));
+      ms[marks[i].first] += t;
+      launches[marks[i].first] += 1;
+    }
+    for (size_t i = 0; i < 2 * nl; ++i)
+      if (launches[i]) ms[i] /= double(launches[i]);
+    return LBM_OK;
+  };
+  int rc = body();
+  cleanup();
+  return rc;
+}
+
 int lbm_synchronize(lbm_forest* f) {
   if (!f) return fail(LBM_E_INVALID, "null pointer");
   HIP_TRY(hipSetDevice(f->device));

@@ -1,0 +1,134 @@
+// Device-side lattice constants, storage forms and vector access shared by
+// the HIP kernels of the library.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbm {
+namespace dev {
+
+// ---- D3Q19 velocity set (rest, 6 faces, 12 edges; opposites adjacent) ----
+__host__ __device__ constexpr int ex(int a) {
+  return a == 1 || a == 7 || a == 9 || a == 11 || a == 13 ? 1 : (a == 2 || a == 8 || a == 10 || a == 12 || a == 14 ? -1 : 0);
+}
+__host__ __device__ constexpr int ey(int a) {
+  return a == 3 || a == 7 || a == 10 || a == 15 || a == 17 ? 1 : (a == 4 || a == 8 || a == 9 || a == 16 || a == 18 ? -1 : 0);
+}
+__host__ __device__ constexpr int ez(int a) {
+  return a == 5 || a == 11 || a == 14 || a == 15 || a == 18 ? 1 : (a == 6 || a == 12 || a == 13 || a == 16 || a == 17 ? -1 : 0);
+}
+template <typename C>
+__host__ __device__ constexpr C wgt(int a) {
+  return a == 0 ? C(1) / C(3) : (a <= 6 ? C(1) / C(18) : C(1) / C(36));
+}
+
+// ---- storage forms --------------------------------------------------------
+template <typename S>
+struct Form;
+template <>
+struct Form<double> {
+  using C = double;
+  static __device__ __forceinline__ double ld(const double* p) { return *p; }
+  static __device__ __forceinline__ void st(double* p, double v) { *p = v; }
+  static __device__ __forceinline__ double omega(const SweepArgs& a) { return a.omega64; }
+};
+template <>
+struct Form<float> {
+  using C = float;
+  static __device__ __forceinline__ float ld(const float* p) { return *p; }
+  static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
+  static __device__ __forceinline__ float omega(const SweepArgs& a) { return a.omega; }
+};
+template <>
+struct Form<__half> {
+  using C = float;
+  static __device__ __forceinline__ float ld(const __half* p) { return __half2float(*p); }
+  static __device__ __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(v); }
+  static __device__ __forceinline__ float omega(const SweepArgs& a) { return a.omega; }
+};
+
+// ---- vector access: W consecutive cells of one row per lane ----------------
+// Stores are nontemporal: the sweep's output is not read again before the
+// next launch, and streaming it past the caches measured faster.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename S>
+struct Vec;
+template <>
+struct Vec<float> {
+  static constexpr int W = 4;  // 16-byte loads and stores
+  static __device__ __forceinline__ void load(const float* p, float* v) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    v[0] = t.x, v[1] = t.y, v[2] = t.z, v[3] = t.w;
+  }
+  static __device__ __forceinline__ void store(float* p, const float* v) {
+    const f32x4 t = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(t, reinterpret_cast<f32x4*>(p));
+  }
+};
+template <>
+struct Vec<double> {
+  static constexpr int W = 2;  // 16-byte loads and stores
+  static __device__ __forceinline__ void load(const double* p, double* v) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    v[0] = t.x, v[1] = t.y;
+  }
+  static __device__ __forceinline__ void store(double* p, const double* v) {
+    const f64x2 t = {v[0], v[1]};
+    __builtin_nontemporal_store(t, reinterpret_cast<f64x2*>(p));
+  }
+};
+template <>
+struct Vec<__half> {
+  static constexpr int W = 4;  // 8-byte loads and stores
+  static __device__ __forceinline__ void load(const __half* p, float* v) {
+    const uint2 t = *reinterpret_cast<const uint2*>(p);
+    v[0] = __half2float(__ushort_as_half(uint16_t(t.x & 0xFFFFu)));
+    v[1] = __half2float(__ushort_as_half(uint16_t(t.x >> 16)));
+    v[2] = __half2float(__ushort_as_half(uint16_t(t.y & 0xFFFFu)));
+    v[3] = __half2float(__ushort_as_half(uint16_t(t.y >> 16)));
+  }
+  static __device__ __forceinline__ void store(__half* p, const float* v) {
+    u32x2 t;
+    t.x = uint32_t(__half_as_ushort(__float2half_rn(v[0]))) | (uint32_t(__half_as_ushort(__float2half_rn(v[1]))) << 16);
+    t.y = uint32_t(__half_as_ushort(__float2half_rn(v[2]))) | (uint32_t(__half_as_ushort(__float2half_rn(v[3]))) << 16);
+    __builtin_nontemporal_store(t, reinterpret_cast<u32x2*>(p));
+  }
+};
+
+// Cross-lane moves inside 16-lane DPP rows: lane l receives lane l - 1
+// (shift right) or lane l + 1 (shift left).  A cell row of N cells spans
+// N / W <= 16 lanes, aligned to the DPP rows, and the lanes at the two ends
+// of a cell row take their outside value from a separate load.
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowShl1 = 0x101;
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(uint32_t(lo)) | ((long long)hi << 32));
+}
+
+template <typename S, int N>
+struct Geo {
+  static constexpr int W = Vec<S>::W;
+  static constexpr int N3 = N * N * N;
+  static constexpr int CELLS = N3 < 256 * W ? N3 : 256 * W;  // cells per work tile
+  static constexpr int T = CELLS / W;                          // threads per workgroup
+  static constexpr int TPB = N3 / CELLS;                       // tiles per block
+  static constexpr int H = N / 2;
+  static_assert(N / W <= 16, "a cell row must fit one DPP row");
+};
+
+}  // namespace dev
+}  // namespace lbm

@@ -71,6 +71,7 @@ _SIGNATURES = {
     "lbm_set_schedule": [ctypes.c_void_p, ctypes.c_int],
     "lbm_set_launch": [ctypes.c_void_p, ctypes.c_int],
     "lbm_synchronize": [ctypes.c_void_p],
+    "lbm_time_sweeps": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_get_pdfs": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_pdfs": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_lattice": [ctypes.c_void_p, ctypes.c_void_p],
@@ -247,6 +248,14 @@ class Forest:
 
     def step_coarse(self, n_steps: int = 1):
         _check(self._lib.lbm_step_coarse(self._h, int(n_steps)))
+
+    def time_sweeps(self, n_steps: int = 1):
+        """Advance n_steps coarse steps with a HIP event pair around every
+        sweep launch; returns {(level, substep): (mean ms, launches)}."""
+        ms = np.zeros(2 * self.num_levels)
+        cnt = np.zeros(2 * self.num_levels, dtype=np.int64)
+        _check(self._lib.lbm_time_sweeps(self._h, int(n_steps), _ptr(ms), _ptr(cnt)))
+        return {(i // 2, i % 2 + 1): (float(ms[i]), int(cnt[i])) for i in range(2 * self.num_levels) if cnt[i]}
 
     def synchronize(self):
         _check(self._lib.lbm_synchronize(self._h))

@@ -1,0 +1,196 @@
+"""Profiling helpers: workloads to run under rocprofv3 and summaries of its output.
+
+    python -m paper_1508_07982_amd.profiling copy                 # 1 GiB device copy x 3 (counter scale)
+    python -m paper_1508_07982_amd.profiling sweep [--storage f32] [--steps 2]
+    python -m paper_1508_07982_amd.profiling trace-summary  RESULTS_DIR OUT.txt --command "..."
+    python -m paper_1508_07982_amd.profiling traffic-summary COPY_FETCH COPY_WRITE SWEEP_FETCH SWEEP_WRITE OUT.txt
+            --command "..."
+
+The sweep workload is the benchmark grid (sphere shell, 4^3 roots of 32^3
+cells, 121.4 M cells) stepped with one launch per level substep, so every
+sweep dispatch shows up in the trace.  FETCH_SIZE and WRITE_SIZE (KiB per
+dispatch) are scaled by what the same counters read for a copy of a known
+byte count; the result is the HBM traffic of one finest-level sweep launch.
+"""
+
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+COPY_BYTES = 1 << 30
+
+
+def sweep_sources_hash(storage: str = "f32") -> str:
+    h = hashlib.sha256()
+    for f in ("sweep.hpp", "lattice.hpp", "kernels.hpp", f"sweep_{storage}.hip"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def run_copy():
+    import torch
+    a = torch.zeros(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {COPY_BYTES} bytes x 3", flush=True)
+
+
+def run_sweep(storage: str, steps: int):
+    sys.path.insert(0, ROOT)
+    from paper_1508_07982_amd import lbm
+    from paper_1508_07982_amd import workloads as W
+    w = W.config_sphere(32, 4)
+    g = lbm.Forest(w.R, w.n, w.max_level, refine=w.refine, storage=storage)
+    rho, u = W.initial_field(w, g.leaves())
+    g.set_level_omega(w.omega0)
+    g.set_schedule("direct")
+    g.init_pdfs(rho, u)
+    del rho, u
+    g.step_coarse(steps)
+    g.synchronize()
+    tiles = {L: g.level_stats(L)["work_tiles"] for L in range(g.num_levels)}
+    print("work tiles per level", tiles, flush=True)
+    g.close()
+
+
+def _finest_tiles():
+    sys.path.insert(0, ROOT)
+    from paper_1508_07982_amd import lbm
+    from paper_1508_07982_amd import workloads as W
+    w = W.config_sphere(32, 4)
+    return {L: lbm.plan_level_stats(w.R, w.n, w.max_level, L, refine=w.refine)["work_tiles"]
+            for L in range(w.max_level + 1)}
+
+
+def _db(path):
+    if os.path.isdir(path):
+        hits = glob.glob(os.path.join(path, "**", "*_results.db"), recursive=True)
+        if not hits:
+            raise FileNotFoundError(f"no *_results.db under {path}")
+        path = hits[0]
+    return sqlite3.connect(path)
+
+
+def trace_summary(results: str, out: str, command: str):
+    db = _db(results)
+    rows = list(db.execute("select name, duration, grid_x, workgroup_x from kernels"))
+    tiles = _finest_tiles()
+    level_of_grid = {}
+    for L, t in tiles.items():
+        level_of_grid.setdefault(t, L)
+    stats = {}
+    for name, dur, gx, wx in rows:
+        key = name.rsplit("(", 1)[0]
+        stats.setdefault(key, []).append(dur)
+    per_level = {}
+    for name, dur, gx, wx in rows:
+        if "sweep_kernel" in name:
+            L = level_of_grid.get(gx // max(wx, 1))
+            per_level.setdefault((name.rsplit("(", 1)[0], L), []).append(dur)
+    with open(out, "w") as fh:
+        fh.write(f"# rocprofv3 --kernel-trace --stats summary\n# command: {command}\n")
+        fh.write("# durations in microseconds\n\n")
+        fh.write(f"{'kernel':70s} {'calls':>6s} {'total_us':>12s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}\n")
+        for k, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+            fh.write(f"{k[:70]:70s} {len(v):6d} {sum(v) / 1e3:12.1f} {sum(v) / len(v) / 1e3:10.2f} "
+                     f"{min(v) / 1e3:10.2f} {max(v) / 1e3:10.2f}\n")
+        fh.write("\n# sweep launches by level (level from the grid size = work tiles of that level)\n")
+        for (k, L), v in sorted(per_level.items(), key=lambda kv: (kv[0][0], -1 if kv[0][1] is None else kv[0][1])):
+            fh.write(f"{k[:60]:60s} level {L}: {len(v):5d} launches, avg {sum(v) / len(v) / 1e3:10.2f} us\n")
+    print(open(out).read())
+
+
+def _counter(path, counter):
+    db = _db(path)
+    return list(db.execute("select name, counter_value from pmc_events where counter_name = ?", (counter,)))
+
+
+def traffic_summary(copy_fetch, copy_write, sweep_fetch, sweep_write, out, command, storage="f32"):
+    cf = [v for n, v in _counter(copy_fetch, "FETCH_SIZE") if "copy" in n.lower() or "elementwise" in n.lower()]
+    cw = [v for n, v in _counter(copy_write, "WRITE_SIZE") if "copy" in n.lower() or "elementwise" in n.lower()]
+    if not cf or not cw:
+        raise RuntimeError("copy kernel not found in the copy profiles")
+    fetch_scale = COPY_BYTES / (max(cf) * 1024.0)
+    write_scale = COPY_BYTES / (max(cw) * 1024.0)
+    tiles = _finest_tiles()
+    Lf = max(tiles)
+    sys.path.insert(0, ROOT)
+    db = _db(sweep_fetch)
+    fin_f = [v for n, v, g, w in db.execute(
+        "select p.name, p.counter_value, k.grid_x, k.workgroup_x from pmc_events p join kernels k "
+        "on p.dispatch_id = k.dispatch_id where p.counter_name = 'FETCH_SIZE'") if "sweep_kernel" in n
+        and g // max(w, 1) == tiles[Lf]]
+    db = _db(sweep_write)
+    fin_w = [v for n, v, g, w in db.execute(
+        "select p.name, p.counter_value, k.grid_x, k.workgroup_x from pmc_events p join kernels k "
+        "on p.dispatch_id = k.dispatch_id where p.counter_name = 'WRITE_SIZE'") if "sweep_kernel" in n
+        and g // max(w, 1) == tiles[Lf]]
+    if not fin_f or not fin_w:
+        raise RuntimeError("finest-level sweep dispatches not found")
+    fetch = sum(fin_f) / len(fin_f) * 1024.0 * fetch_scale
+    write = sum(fin_w) / len(fin_w) * 1024.0 * write_scale
+    from paper_1508_07982_amd import workloads as W
+    from paper_1508_07982_amd import lbm
+    w = W.config_sphere(32, 4)
+    cells = lbm.plan_level_stats(w.R, w.n, w.max_level, Lf, refine=w.refine)["interior_cells"]
+    s = lbm.STORAGE_BYTES[storage]
+    alg = 38 * s * cells
+    with open(out, "w") as fh:
+        fh.write("# HBM traffic of one finest-level sweep launch, from rocprofv3 --pmc passes\n")
+        fh.write(f"# command: {command}\n")
+        fh.write(f"# copy of {COPY_BYTES} bytes: FETCH_SIZE {max(cf):.0f} KiB, WRITE_SIZE {max(cw):.0f} KiB\n")
+        fh.write(f"storage: {storage}\n")
+        fh.write(f"kernel_sha256_16: {sweep_sources_hash(storage)}\n")
+        fh.write(f"level: {Lf}\n")
+        fh.write(f"interior_cells: {cells}\n")
+        fh.write(f"fetch_scale: {fetch_scale:.4f}\n")
+        fh.write(f"write_scale: {write_scale:.4f}\n")
+        fh.write(f"fetch_bytes_per_launch: {fetch:.0f}\n")
+        fh.write(f"write_bytes_per_launch: {write:.0f}\n")
+        fh.write(f"hbm_bytes_per_launch: {fetch + write:.0f}\n")
+        fh.write(f"algorithmic_bytes_per_launch: {alg}\n")
+        fh.write(f"traffic_over_algorithmic: {(fetch + write) / alg:.4f}\n")
+        fh.write(f"launches_averaged: {len(fin_f)}\n")
+    print(open(out).read())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    sub.add_parser("copy")
+    s = sub.add_parser("sweep")
+    s.add_argument("--storage", default="f32")
+    s.add_argument("--steps", type=int, default=2)
+    t = sub.add_parser("trace-summary")
+    t.add_argument("results")
+    t.add_argument("out")
+    t.add_argument("--command", required=True)
+    tr = sub.add_parser("traffic-summary")
+    for k in ("copy_fetch", "copy_write", "sweep_fetch", "sweep_write", "out"):
+        tr.add_argument(k)
+    tr.add_argument("--command", required=True)
+    tr.add_argument("--storage", default="f32")
+    a = ap.parse_args()
+    if a.cmd == "copy":
+        run_copy()
+    elif a.cmd == "sweep":
+        run_sweep(a.storage, a.steps)
+    elif a.cmd == "trace-summary":
+        trace_summary(a.results, a.out, a.command)
+    else:
+        traffic_summary(a.copy_fetch, a.copy_write, a.sweep_fetch, a.sweep_write, a.out, a.command, a.storage)
+
+
+if __name__ == "__main__":
+    main()
