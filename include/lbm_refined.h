@@ -163,6 +163,19 @@ int lbm_set_schedule(lbm_forest *f, int schedule);
  * graph.  Results do not depend on it. */
 int lbm_set_launch(lbm_forest *f, int persistent);
 
+/* Dynamic regrid (the paper names dynamic refinement as future work; the
+ * operators are its own).  flags[i] for the i-th leaf in canonical order:
+ * > 0 split it (if below the max_level given at creation), < 0 merge it with
+ * its 7 siblings if all 8 are leaves flagged < 0, 0 keep.  Order: splits,
+ * 2:1 balance by further splits, then merges from the finest level down,
+ * each kept only if no leaf two levels finer than the merged parent touches
+ * it.  PDFs: unchanged blocks keep their state; a new fine block takes, in
+ * all 19 directions, the post-streaming values of the coarse cell containing
+ * each cell (eq. ctof), a merged block the mean of its 8 children (eq. ftoc),
+ * and is then collided.  count = number of leaves.  Synchronous; afterwards
+ * sizes, leaves and the canonical order refer to the new forest. */
+int lbm_regrid(lbm_forest *f, const int8_t *flags, int64_t count);
+
 /* Instrumented stepping: advance n_steps >= 1 coarse steps with direct
  * launches, a hipEvent pair on the forest's stream around every sweep, and
  * return the mean launch duration in milliseconds and the launch count per

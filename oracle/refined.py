@@ -105,6 +105,8 @@ class RefinedOracle:
         self.n = forest.n
         self.num_levels = forest.max_level + 1
         self.tables = build_tables(forest, coalescence)
+        self._omega0 = omega0
+        self._coalescence = coalescence
         self.omega = [float(omega_level(float(omega0), L)) for L in range(self.num_levels)]
         self.F = []
         self.G = []
@@ -177,6 +179,18 @@ class RefinedOracle:
         out = np.zeros(self.num_levels, dtype=np.int64)
         _load().orc_stream_calls(_ptr(out), self.num_levels, int(reset))
         return out
+
+    def regrid(self, flags, max_level: int):
+        """New oracle on the regridded forest with the remapped state (see
+        oracle/regrid.py); omega_0 and the coalescence reading are kept."""
+        from .regrid import regrid_forest, remap_interior
+        nf = regrid_forest(self.forest, flags, max_level)
+        new = RefinedOracle(nf, self._omega0, self._coalescence)
+        pdfs = remap_interior(self.forest, [self.interior_pdfs(L) for L in range(self.num_levels)], nf)
+        for L in range(new.num_levels):
+            new.F[L][:] = np.nan
+            new.F[L][:new.n_int(L)] = pdfs[L]
+        return new
 
     # -- outputs -------------------------------------------------------------
     def moments(self):

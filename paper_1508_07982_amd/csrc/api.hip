@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <unordered_map>
+#include <unordered_set>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -68,6 +70,7 @@ struct LevelDev {
   int32_t* fine_nbr = nullptr;
   int32_t* work = nullptr;
   double omega = 0.0;
+  std::vector<void*> allocs;  // device memory owned by this level
 };
 
 struct Op {
@@ -90,7 +93,11 @@ struct lbm_forest {
   int persistent = 0;
   int num_cu = 256;
   bool omega_set = false;
-  std::vector<int> rot;  // per level: buffer holding the current state
+  std::vector<int> rot;       // per level: buffer holding the current state
+  std::vector<int> rot_prev;  // the same at the start of the last coarse step
+  int64_t steps_since_state = 0;  // coarse steps since the state was set (init, set_pdfs, regrid)
+  int max_level = 0;              // deepest level a regrid may create
+  double omega0 = 0.0;
   std::map<std::vector<int>, hipGraphExec_t> graphs;
   int* d_err = nullptr;
   double* d_partials = nullptr;
@@ -100,6 +107,8 @@ struct lbm_forest {
     (void)hipSetDevice(device);
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     for (void* p : allocations) (void)hipFree(p);
+    for (auto& v : lv)
+      for (void* p : v.allocs) (void)hipFree(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -107,7 +116,7 @@ struct lbm_forest {
 namespace {
 
 template <typename T>
-int dev_alloc(lbm_forest* f, T** p, size_t count) {
+int dev_alloc(std::vector<void*>& owner, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) return LBM_OK;
   void* q = nullptr;
@@ -117,18 +126,59 @@ int dev_alloc(lbm_forest* f, T** p, size_t count) {
     return fail(e == hipErrorOutOfMemory ? LBM_E_OOM : LBM_E_HIP, "hipMalloc(%zu bytes): %s", count * sizeof(T),
                 hipGetErrorString(e));
   }
-  f->allocations.push_back(q);
+  owner.push_back(q);
   *p = static_cast<T*>(q);
   return LBM_OK;
 }
 
 template <typename T>
-int upload(lbm_forest* f, T** p, const std::vector<T>& v) {
-  int rc = dev_alloc(f, p, v.size());
+int upload(std::vector<void*>& owner, T** p, const std::vector<T>& v) {
+  int rc = dev_alloc(owner, p, v.size());
   if (rc) return rc;
   if (!v.empty()) HIP_TRY(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   return LBM_OK;
 }
+
+// Device storage and tables of every level of `tabs`; buffers zeroed.
+int make_levels(int n, size_t s, const std::vector<LevelTables>& tabs, std::vector<LevelDev>& lv) {
+  const size_t n3 = size_t(n) * n * n;
+  lv.assign(tabs.size(), LevelDev{});
+  int rc;
+  for (size_t L = 0; L < tabs.size(); ++L) {
+    const LevelTables& t = tabs[L];
+    LevelDev& v = lv[L];
+    v.nblocks = t.nblocks;
+    v.nwork = int(t.work.size());
+    v.tiles_per_block = t.tiles_per_block;
+    v.ncells = int64_t(t.nblocks) * int64_t(n3);
+    v.plane = uint64_t(t.nblocks) * n3;
+    if (v.plane >= (uint64_t(1) << 32))
+      return fail(LBM_E_INVALID, "level %zu holds %llu cells; at most 2^32 - 1 per level are addressable", L,
+                  (unsigned long long)v.plane);
+    const size_t bytes = size_t(v.plane) * 19 * s;
+    v.nbuf = L == 0 ? 2 : 3;
+    for (int b = 0; b < v.nbuf; ++b) {
+      uint8_t* p = nullptr;
+      if ((rc = dev_alloc(v.allocs, &p, bytes))) return rc;
+      if (bytes) HIP_TRY(hipMemset(p, 0, bytes));
+      v.buf[b] = p;
+    }
+    if ((rc = upload(v.allocs, &v.nbr, t.nbr))) return rc;
+    if ((rc = upload(v.allocs, &v.flags, t.flags))) return rc;
+    if ((rc = upload(v.allocs, &v.fine_index, t.fine_index))) return rc;
+    if ((rc = upload(v.allocs, &v.fine_nbr, t.fine_nbr))) return rc;
+    if ((rc = upload(v.allocs, &v.work, t.work))) return rc;
+  }
+  return LBM_OK;
+}
+
+void free_levels(std::vector<LevelDev>& lv) {
+  for (auto& v : lv)
+    for (void* p : v.allocs) (void)hipFree(p);
+  lv.clear();
+}
+
+void set_level_omegas(lbm_forest* f);
 
 void invalidate_graphs(lbm_forest* f) {
   for (auto& g : f->graphs) (void)hipGraphExecDestroy(g.second);
@@ -180,6 +230,7 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   a.work = d.work;
   a.nwork = d.nwork;
   a.substep = substep;
+  a.collide = 1;
   a.nbr = d.nbr;
   a.flags = d.flags;
   a.fine_index = d.fine_index;
@@ -231,6 +282,13 @@ int capture_graph(lbm_forest* f, const std::vector<Op>& ops, hipGraphExec_t* out
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(LBM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
   return LBM_OK;
+}
+
+void set_level_omegas(lbm_forest* f) {
+  for (size_t L = 0; L < f->lv.size(); ++L) {
+    const double p = std::ldexp(1.0, int(L));
+    f->lv[L].omega = 2.0 * f->omega0 / (2.0 * p + (1.0 - p) * f->omega0);  // eq. omega_scaling_0
+  }
 }
 
 int check_err_flag(lbm_forest* f) {
@@ -373,37 +431,13 @@ int lbm_create_block_forest(const lbm_forest_desc* d, lbm_forest** out) {
   }
 
   const size_t s = storage_bytes(f->storage);
-  const size_t n3 = size_t(n) * n * n;
-  f->lv.resize(f->tabs.size());
+  f->max_level = d->max_level;
+  if ((rc = make_levels(n, s, f->tabs, f->lv))) return rc;
   f->rot.assign(f->tabs.size(), 0);
-  for (size_t L = 0; L < f->tabs.size(); ++L) {
-    const LevelTables& t = f->tabs[L];
-    LevelDev& v = f->lv[L];
-    v.nblocks = t.nblocks;
-    v.nwork = int(t.work.size());
-    v.tiles_per_block = t.tiles_per_block;
-    v.ncells = int64_t(t.nblocks) * int64_t(n3);
-    v.plane = uint64_t(t.nblocks) * n3;
-    if (v.plane >= (uint64_t(1) << 32))
-      return fail(LBM_E_INVALID, "level %zu holds %llu cells; at most 2^32 - 1 per level are addressable", L,
-                  (unsigned long long)v.plane);
-    const size_t bytes = size_t(v.plane) * 19 * s;
-    v.nbuf = L == 0 ? 2 : 3;
-    for (int b = 0; b < v.nbuf; ++b) {
-      uint8_t* p = nullptr;
-      if ((rc = dev_alloc(f.get(), &p, bytes))) return rc;
-      if (bytes) HIP_TRY(hipMemset(p, 0, bytes));
-      v.buf[b] = p;
-    }
-    if ((rc = upload(f.get(), &v.nbr, t.nbr))) return rc;
-    if ((rc = upload(f.get(), &v.flags, t.flags))) return rc;
-    if ((rc = upload(f.get(), &v.fine_index, t.fine_index))) return rc;
-    if ((rc = upload(f.get(), &v.fine_nbr, t.fine_nbr))) return rc;
-    if ((rc = upload(f.get(), &v.work, t.work))) return rc;
-  }
-  if ((rc = dev_alloc(f.get(), &f->d_err, 1))) return rc;
+  f->rot_prev = f->rot;
+  if ((rc = dev_alloc(f->allocations, &f->d_err, 1))) return rc;
   HIP_TRY(hipMemset(f->d_err, 0, sizeof(int)));
-  if ((rc = dev_alloc(f.get(), &f->d_partials, size_t(kReduceGrid) * 5 * f->lv.size()))) return rc;
+  if ((rc = dev_alloc(f->allocations, &f->d_partials, size_t(kReduceGrid) * 5 * 21))) return rc;
   HIP_TRY(hipDeviceSynchronize());
   *out = f.release();
   g_err.clear();
@@ -467,10 +501,8 @@ int lbm_level_stats(const lbm_forest* f, int level, int64_t out[8]) {
 int lbm_set_level_omega(lbm_forest* f, double omega0) {
   if (!f) return fail(LBM_E_INVALID, "null pointer");
   if (!(omega0 >= 0.0 && omega0 < 2.0)) return fail(LBM_E_INVALID, "omega0 must lie in [0, 2)");
-  for (size_t L = 0; L < f->lv.size(); ++L) {
-    const double p = std::ldexp(1.0, int(L));
-    f->lv[L].omega = 2.0 * omega0 / (2.0 * p + (1.0 - p) * omega0);  // eq. omega_scaling_0
-  }
+  f->omega0 = omega0;
+  set_level_omegas(f);
   f->omega_set = true;
   invalidate_graphs(f);
   return LBM_OK;
@@ -503,6 +535,7 @@ int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
     HIP_TRY(hipMemcpyAsync(d_u, u, total * 3 * sizeof(double), hipMemcpyHostToDevice, f->stream));
     int64_t off = 0;
     std::fill(f->rot.begin(), f->rot.end(), 0);
+    f->steps_since_state = 0;
     for (size_t L = 0; L < f->lv.size(); ++L) {
       const LevelDev& v = f->lv[L];
       HIP_TRY(launch_init(f->storage, f->n, v.buf[0], v.plane, d_rho + off, d_u + 3 * off, v.ncells, f->stream));
@@ -542,6 +575,8 @@ int lbm_step_coarse(lbm_forest* f, int n_steps) {
     std::vector<int> r = f->rot;
     std::vector<Op> ops;
     emit(f, 0, 1, r, nullptr, ops);
+    f->rot_prev = f->rot;
+    f->steps_since_state++;
     if (f->schedule == LBM_SCHED_GRAPH) {
       auto it = f->graphs.find(f->rot);
       if (it == f->graphs.end()) {
@@ -577,6 +612,8 @@ int lbm_time_sweeps(lbm_forest* f, int n_steps, double* ms, int64_t* launches) {
       std::vector<int> r = f->rot;
       std::vector<Op> ops;
       emit(f, 0, 1, r, nullptr, ops);
+      f->rot_prev = f->rot;
+      f->steps_since_state++;
       for (const Op& op : ops) {
         if (op.args.nwork <= 0) continue;
         hipEvent_t e0, e1;
@@ -606,6 +643,175 @@ int lbm_time_sweeps(lbm_forest* f, int n_steps, double* ms, int64_t* launches) {
     return LBM_OK;
   };
   int rc = body();
+  cleanup();
+  return rc;
+}
+
+int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
+  if (!f || (!flags && count)) return fail(LBM_E_INVALID, "null pointer");
+  HIP_TRY(hipSetDevice(f->device));
+  int rc = check_err_flag(f);
+  if (rc) return rc;
+  std::string err;
+  Forest nf;
+  if ((rc = f->forest.regrid(flags, count, f->max_level, nf, err))) return fail(rc, "%s", err.c_str());
+  std::vector<LevelTables> ntabs;
+  if ((rc = build_level_tables(nf, sweep_tile_cells(f->storage, f->n), ntabs, err))) return fail(rc, "%s", err.c_str());
+
+  const int n = f->n;
+  const size_t n3 = size_t(n) * n * n;
+  const size_t sb = storage_bytes(f->storage);
+  const int nold = int(f->lv.size());
+  // old leaves by key
+  std::unordered_map<uint64_t, std::pair<int, int>> old_slot;
+  for (int L = 0; L < nold; ++L) {
+    const auto& lv = f->forest.level_leaves(L);
+    for (int b = 0; b < int(lv.size()); ++b) old_slot[block_key(L, lv[b].x, lv[b].y, lv[b].z)] = {L, b};
+  }
+  std::unordered_set<uint64_t> new_keys;
+  for (int L = 0; L < nf.num_levels(); ++L)
+    for (const Leaf& l : nf.level_leaves(L)) new_keys.insert(block_key(L, l.x, l.y, l.z));
+
+  std::vector<void*> scratch;  // freed on every exit path below
+  auto cleanup = [&]() {
+    for (void* p : scratch) (void)hipFree(p);
+  };
+  auto body = [&]() -> int {
+    // post-streaming values of the old blocks that change (section 4: the
+    // state between coarse steps is post-streaming): re-run each level's
+    // last launch of the last coarse step without the collision, into a
+    // scratch buffer; its inputs are still intact
+    const bool have_post = f->steps_since_state > 0;
+    std::vector<const void*> post(nold, nullptr), cur(nold, nullptr);
+    std::vector<uint64_t> planes(nold, 0);
+    std::vector<Op> ops;
+    if (have_post) {
+      std::vector<int> r = f->rot_prev;
+      emit(f, 0, 1, r, nullptr, ops);
+    }
+    for (int L = 0; L < nold; ++L) {
+      cur[L] = current_buffer(f, L);
+      planes[L] = f->lv[L].plane;
+      post[L] = cur[L];
+      if (!have_post) continue;
+      std::vector<int32_t> work;
+      const auto& lv = f->forest.level_leaves(L);
+      const int tpb = f->lv[L].tiles_per_block;
+      for (int b = 0; b < int(lv.size()); ++b)
+        if (!new_keys.count(block_key(L, lv[b].x, lv[b].y, lv[b].z)))
+          for (int t = 0; t < tpb; ++t) work.push_back(b * tpb + t);
+      if (work.empty()) continue;
+      const Op* last = nullptr;
+      for (const Op& op : ops)
+        if (op.level == L) last = &op;
+      if (!last) return fail(LBM_E_STATE, "no launch recorded for level %d", L);
+      uint8_t* tmp = nullptr;
+      int32_t* dwork = nullptr;
+      int rc2;
+      if ((rc2 = dev_alloc(scratch, &tmp, size_t(planes[L]) * 19 * sb))) return rc2;
+      if ((rc2 = upload(scratch, &dwork, work))) return rc2;
+      SweepArgs a = last->args;
+      a.nxt = tmp;
+      a.collide = 0;
+      a.work = dwork;
+      a.nwork = int32_t(work.size());
+      HIP_TRY(launch_sweep(f->storage, n, a, a.nwork, f->stream));
+      post[L] = tmp;
+    }
+    const void** d_cur = nullptr;
+    const void** d_post = nullptr;
+    uint64_t* d_planes = nullptr;
+    int rc2;
+    if ((rc2 = upload(scratch, &d_cur, cur))) return rc2;
+    if ((rc2 = upload(scratch, &d_post, post))) return rc2;
+    if ((rc2 = upload(scratch, &d_planes, planes))) return rc2;
+
+    std::vector<LevelDev> nlv;
+    if ((rc2 = make_levels(n, sb, ntabs, nlv))) {
+      free_levels(nlv);
+      return rc2;
+    }
+    for (int L = 0; L < int(ntabs.size()); ++L) {
+      const auto& lv = nf.level_leaves(L);
+      std::vector<RemapBlock> rb(lv.size());
+      for (size_t b = 0; b < lv.size(); ++b) {
+        const Leaf& l = lv[b];
+        RemapBlock& e = rb[b];
+        std::fill(e.slot, e.slot + 8, 0);
+        e.off[0] = e.off[1] = e.off[2] = 0;
+        e.shift = 0;
+        auto it = old_slot.find(block_key(L, l.x, l.y, l.z));
+        if (it != old_slot.end()) {
+          e.mode = 0;
+          e.src_level = L;
+          e.slot[0] = it->second.second;
+          continue;
+        }
+        bool found = false;
+        for (int up = 1; up <= L && !found; ++up) {
+          auto a = old_slot.find(block_key(L - up, l.x >> up, l.y >> up, l.z >> up));
+          if (a == old_slot.end()) continue;
+          e.mode = 1;
+          e.src_level = L - up;
+          e.shift = up;
+          e.slot[0] = a->second.second;
+          e.off[0] = ((l.x * n) >> up) - (l.x >> up) * n;
+          e.off[1] = ((l.y * n) >> up) - (l.y >> up) * n;
+          e.off[2] = ((l.z * n) >> up) - (l.z >> up) * n;
+          found = true;
+        }
+        if (found) continue;
+        e.mode = 2;
+        e.src_level = L + 1;
+        for (int o = 0; o < 8; ++o) {
+          auto c = old_slot.find(block_key(L + 1, 2 * l.x + (o & 1), 2 * l.y + ((o >> 1) & 1), 2 * l.z + (o >> 2)));
+          if (c == old_slot.end()) {
+            free_levels(nlv);
+            return fail(LBM_E_STATE, "regrid: block (%d,%d,%d,%d) has no source", L, l.x, l.y, l.z);
+          }
+          e.slot[o] = c->second.second;
+        }
+      }
+      RemapBlock* d_rb = nullptr;
+      if ((rc2 = upload(scratch, &d_rb, rb))) {
+        free_levels(nlv);
+        return rc2;
+      }
+      RemapArgs ra;
+      ra.dst = nlv[L].buf[0];
+      ra.dst_plane = nlv[L].plane;
+      ra.blocks = d_rb;
+      ra.ncells = int64_t(lv.size()) * int64_t(n3);
+      ra.old_cur = d_cur;
+      ra.old_post = d_post;
+      ra.old_plane = d_planes;
+      ra.collide = have_post ? 1 : 0;
+      const double p2 = std::ldexp(1.0, L);
+      ra.omega64 = 2.0 * f->omega0 / (2.0 * p2 + (1.0 - p2) * f->omega0);
+      ra.omega = float(ra.omega64);
+      hipError_t e = launch_remap(f->storage, n, ra, f->stream);
+      if (e != hipSuccess) {
+        free_levels(nlv);
+        return fail(LBM_E_HIP, "remap: %s", hipGetErrorString(e));
+      }
+    }
+    hipError_t e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) {
+      free_levels(nlv);
+      return fail(LBM_E_HIP, "regrid: %s", hipGetErrorString(e));
+    }
+    invalidate_graphs(f);
+    free_levels(f->lv);
+    f->lv = std::move(nlv);
+    f->tabs = std::move(ntabs);
+    f->forest = std::move(nf);
+    f->rot.assign(f->lv.size(), 0);
+    f->rot_prev = f->rot;
+    f->steps_since_state = 0;
+    set_level_omegas(f);
+    return LBM_OK;
+  };
+  rc = body();
   cleanup();
   return rc;
 }
@@ -679,6 +885,7 @@ int lbm_set_pdfs(lbm_forest* f, const double* h) {
     auto body = [&]() -> int {
       HIP_TRY(hipMemcpyAsync(d, h + 19 * off, v.ncells * 19 * sizeof(double), hipMemcpyHostToDevice, f->stream));
       HIP_TRY(launch_set_pdfs(f->storage, f->n, current_buffer_mut(f, int(L)), v.plane, d, v.ncells, f->stream));
+      f->steps_since_state = 0;
       HIP_TRY(hipStreamSynchronize(f->stream));
       return LBM_OK;
     };

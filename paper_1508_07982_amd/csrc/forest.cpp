@@ -202,6 +202,80 @@ int Forest::build_from_callback(const int R_[3], int n_, int max_level_, int (*r
   return LBM_OK;
 }
 
+int Forest::regrid(const int8_t* flags, int64_t count, int max_level_, Forest& out, std::string& err) const {
+  int64_t total = 0;
+  for (int L = 0; L < num_levels(); ++L) total += int64_t(by_level_[L].size());
+  if (count != total) {
+    err = "one flag per leaf expected";
+    return LBM_E_INVALID;
+  }
+  out = Forest();
+  for (int a = 0; a < 3; ++a) out.R[a] = R[a];
+  out.n = n;
+  out.leaves_ = leaves_;
+  std::unordered_set<uint64_t> coarsen;
+  int64_t i = 0;
+  for (int L = 0; L < num_levels(); ++L)
+    for (const Leaf& l : by_level_[L]) {
+      const int8_t fl = flags[i++];
+      if (fl > 0 && L < max_level_) out.split(l);
+      if (fl < 0 && L > 0) coarsen.insert(block_key(L, l.x, l.y, l.z));
+    }
+  out.enforce_balance();
+  int lmax = 0;
+  for (uint64_t k : out.leaves_) lmax = std::max(lmax, unpack(k).level);
+  for (int L = lmax; L >= 1; --L) {
+    // parents whose 8 children are all leaves flagged for coarsening
+    std::vector<Leaf> parents;
+    std::unordered_set<uint64_t> seen;
+    for (uint64_t k : coarsen) {
+      const Leaf c = unpack(k);
+      if (c.level != L) continue;
+      const Leaf p{L - 1, c.x >> 1, c.y >> 1, c.z >> 1};
+      if (!seen.insert(block_key(p.level, p.x, p.y, p.z)).second) continue;
+      bool all = true;
+      for (int o = 0; o < 8 && all; ++o) {
+        const uint64_t ck = block_key(L, 2 * p.x + (o & 1), 2 * p.y + ((o >> 1) & 1), 2 * p.z + (o >> 2));
+        all = coarsen.count(ck) && out.leaves_.count(ck);
+      }
+      if (all) parents.push_back(p);
+    }
+    for (const Leaf& p : parents) {
+      bool ok = true;
+      for (int d = 0; d < 27 && ok; ++d) {
+        if (d == 13) continue;
+        // a leaf finer than L touching the parent's region forbids the merge
+        const int qx = p.x + d % 3 - 1, qy = p.y + (d / 3) % 3 - 1, qz = p.z + d / 9 - 1;
+        const int cl = out.covering_level(L - 1, qx, qy, qz);
+        if (cl > L - 1) {
+          // the neighbour position is split: look at its children next to p
+          const int wx = wrap(qx, out.dims(L - 1, 0)), wy = wrap(qy, out.dims(L - 1, 1)), wz = wrap(qz, out.dims(L - 1, 2));
+          for (int o = 0; o < 8 && ok; ++o) {
+            const int cx = 2 * wx + (o & 1), cy = 2 * wy + ((o >> 1) & 1), cz = 2 * wz + (o >> 2);
+            // child touches p's region only if it lies on the side facing p
+            const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+            if ((dx == 1 && (o & 1)) || (dx == -1 && !(o & 1)) || (dy == 1 && ((o >> 1) & 1)) ||
+                (dy == -1 && !((o >> 1) & 1)) || (dz == 1 && (o >> 2)) || (dz == -1 && !(o >> 2)))
+              continue;
+            if (out.covering_level(L, cx, cy, cz) > L) ok = false;
+          }
+        }
+      }
+      if (!ok) continue;
+      for (int o = 0; o < 8; ++o)
+        out.leaves_.erase(block_key(L, 2 * p.x + (o & 1), 2 * p.y + ((o >> 1) & 1), 2 * p.z + (o >> 2)));
+      out.leaves_.insert(block_key(L - 1, p.x, p.y, p.z));
+    }
+  }
+  if (!out.check_cover(err)) return LBM_E_COVER;
+  if (!out.balanced()) {
+    err = "regrid produced an unbalanced forest";
+    return LBM_E_UNBALANCED;
+  }
+  out.finalize();
+  return LBM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // level tables
 // ---------------------------------------------------------------------------

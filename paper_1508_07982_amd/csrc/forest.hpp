@@ -57,6 +57,13 @@ class Forest {
   bool is_leaf(int level, int x, int y, int z) const;
   int dims(int level, int axis) const { return R[axis] << level; }
 
+  // Dynamic regrid.  flags[i] for the i-th leaf in canonical order: > 0 split
+  // it (if below max_level), < 0 merge it with its 7 siblings if all 8 are
+  // leaves flagged < 0, 0 keep.  Order: splits, 2:1 balance by further
+  // splits, then merges from the finest level down, each only if no leaf
+  // finer than the siblings touches their parent.  Returns the new forest.
+  int regrid(const int8_t* flags, int64_t count, int max_level_, Forest& out, std::string& err) const;
+
   // Leaves of one level in canonical order.
   const std::vector<Leaf>& level_leaves(int level) const { return by_level_[level]; }
   int num_levels() const { return max_level + 1; }

@@ -113,6 +113,64 @@ __global__ void __launch_bounds__(kReduceThreads) reduce_kernel(const S* buf, ui
   }
 }
 
+template <typename S, int N>
+__global__ void remap_kernel(RemapArgs a) {
+  using C = typename Form<S>::C;
+  constexpr int N3 = N * N * N, H = N / 2;
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= a.ncells) return;
+  const int64_t b = idx / N3;
+  const int local = int(idx - b * N3);
+  const int i = local % N, j = (local / N) % N, k = local / (N * N);
+  const RemapBlock rb = a.blocks[b];
+  C h[19];
+  if (rb.mode == 0 || rb.mode == 1) {
+    const int src = rb.mode == 0 ? local
+                                 : (rb.off[0] + (i >> rb.shift)) + N * ((rb.off[1] + (j >> rb.shift)) +
+                                                                       N * (rb.off[2] + (k >> rb.shift)));
+    const S* p = static_cast<const S*>(rb.mode == 0 ? a.old_cur[rb.src_level] : a.old_post[rb.src_level]);
+    const uint64_t plane = a.old_plane[rb.src_level];
+#pragma unroll
+    for (int d = 0; d < 19; ++d) h[d] = Form<S>::ld(p + d * plane + uint64_t(rb.slot[0]) * N3 + src);
+  } else {
+    const int oct = (i >= H ? 1 : 0) | (j >= H ? 2 : 0) | (k >= H ? 4 : 0);
+    const int cx = 2 * (i & (H - 1)), cy = 2 * (j & (H - 1)), cz = 2 * (k & (H - 1));
+    const S* p = static_cast<const S*>(a.old_post[rb.src_level]);
+    const uint64_t plane = a.old_plane[rb.src_level];
+    const uint64_t base = uint64_t(rb.slot[oct]) * N3;
+#pragma unroll
+    for (int d = 0; d < 19; ++d) {
+      C s = C(0);
+      for (int oz = 0; oz < 2; ++oz)
+        for (int oy = 0; oy < 2; ++oy)
+          for (int ox = 0; ox < 2; ++ox) s += Form<S>::ld(p + d * plane + base + (cx + ox) + N * ((cy + oy) + N * (cz + oz)));
+      h[d] = s * C(0.125);
+    }
+  }
+  if (rb.mode != 0 && a.collide) {
+    // SRT collision in shifted form, as in the sweep
+    const C om = sizeof(C) == 8 ? C(a.omega64) : C(a.omega);
+    C drho = 0, ux = 0, uy = 0, uz = 0;
+#pragma unroll
+    for (int d = 0; d < 19; ++d) {
+      drho += h[d];
+      ux += C(ex(d)) * h[d];
+      uy += C(ey(d)) * h[d];
+      uz += C(ez(d)) * h[d];
+    }
+    const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+    for (int d = 0; d < 19; ++d) {
+      const C eu = C(ex(d)) * ux + C(ey(d)) * uy + C(ez(d)) * uz;
+      const C heq = wgt<C>(d) * (drho + C(3) * eu + C(4.5) * eu * eu - usq);
+      h[d] = h[d] + om * (heq - h[d]);
+    }
+  }
+  S* out = static_cast<S*>(a.dst);
+#pragma unroll
+  for (int d = 0; d < 19; ++d) Form<S>::st(out + d * a.dst_plane + idx, h[d]);
+}
+
 template <typename F>
 hipError_t dispatch(int storage, int n, F&& f) {
   auto by_n = [&](auto tag) -> hipError_t {
@@ -197,6 +255,16 @@ hipError_t launch_set_pdfs(int storage, int n, void* buf, uint64_t plane, const 
     constexpr int N = decltype(nn)::value;
     hipLaunchKernelGGL((set_pdfs_kernel<S, N>), dim3(grid_for(ncells, 256)), dim3(256), 0, stream,
                        static_cast<S*>(buf), plane, h, ncells);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_remap(int storage, int n, const RemapArgs& a, hipStream_t stream) {
+  if (a.ncells <= 0) return hipSuccess;
+  return dispatch(storage, n, [&](auto s, auto nn) {
+    using S = decltype(s);
+    constexpr int N = decltype(nn)::value;
+    hipLaunchKernelGGL((remap_kernel<S, N>), dim3(grid_for(a.ncells, 256)), dim3(256), 0, stream, a);
     return hipGetLastError();
   });
 }

@@ -24,6 +24,7 @@ struct SweepArgs {
   const int32_t* work;        // work tiles: slot * tiles_per_block + tile
   int32_t nwork;
   int32_t substep;            // 1 or 2
+  int32_t collide;            // 1: collide interior cells (normal); 0: write the streamed values
   const int32_t* nbr;         // [slot][27]
   const uint32_t* flags;      // [slot]
   const int32_t* fine_index;  // [slot]
@@ -63,5 +64,34 @@ hipError_t launch_set_pdfs(int storage, int n, void* buf, uint64_t plane, const 
 constexpr int kReduceGrid = 1024;
 hipError_t launch_reduce(int storage, int n, const void* buf, uint64_t plane, int64_t ncells, double* out,
                          hipStream_t stream);
+
+// Regrid remap of one new level.  Each new block takes its PDFs from the old
+// forest: mode 0 copies an unchanged block from the old state; mode 1
+// explodes an old ancestor `shift` levels up (eq. ctof: a new cell takes the
+// cell containing it, local offset `off` inside the old block); mode 2
+// averages the 8 old child blocks (eq. ftoc).  Modes 1 and 2 read the old
+// post-streaming values and collide the result with omega when collide != 0.
+struct RemapBlock {
+  int32_t mode;
+  int32_t src_level;
+  int32_t shift;
+  int32_t off[3];
+  int32_t slot[8];
+};
+
+struct RemapArgs {
+  void* dst;                  // new level buffer (state written as slot-major canonical cells)
+  uint64_t dst_plane;
+  const RemapBlock* blocks;   // one per new block
+  int64_t ncells;             // new blocks * n^3
+  const void* const* old_cur;   // per old level: current (post-collision) state
+  const void* const* old_post;  // per old level: post-streaming values of changed blocks
+  const uint64_t* old_plane;    // per old level
+  int32_t collide;
+  float omega;
+  double omega64;
+};
+
+hipError_t launch_remap(int storage, int n, const RemapArgs& a, hipStream_t stream);
 
 }  // namespace lbm

@@ -269,9 +269,11 @@ __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache&
   uint32_t odd = 0;
   pull_all<S, N, SIMPLE>(a, sc, slot, i0, j, k, h, odd);
   if (!SIMPLE && odd) fixups<S, N>(a, sc, slot, fl, i0, j, k, h);
-  const C om = Form<S>::omega(a);
+  if (a.collide) {
+    const C om = Form<S>::omega(a);
 #pragma unroll
-  for (int c = 0; c < W; ++c) collide<C, W>(h, c, om);
+    for (int c = 0; c < W; ++c) collide<C, W>(h, c, om);
+  }
   S* __restrict__ nxt = static_cast<S*>(a.nxt) + uint32_t(slot) * N3 + uint32_t(cell0);
 #pragma unroll
   for (int d = 0; d < 19; ++d) Vec<S>::store(nxt + d * a.plane, h[d]);

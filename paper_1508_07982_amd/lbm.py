@@ -72,6 +72,7 @@ _SIGNATURES = {
     "lbm_set_launch": [ctypes.c_void_p, ctypes.c_int],
     "lbm_synchronize": [ctypes.c_void_p],
     "lbm_time_sweeps": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_regrid": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
     "lbm_get_pdfs": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_pdfs": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_lattice": [ctypes.c_void_p, ctypes.c_void_p],
@@ -256,6 +257,16 @@ class Forest:
         cnt = np.zeros(2 * self.num_levels, dtype=np.int64)
         _check(self._lib.lbm_time_sweeps(self._h, int(n_steps), _ptr(ms), _ptr(cnt)))
         return {(i // 2, i % 2 + 1): (float(ms[i]), int(cnt[i])) for i in range(2 * self.num_levels) if cnt[i]}
+
+    def regrid(self, flags):
+        """Split (> 0), merge (< 0) or keep (0) every leaf (canonical order)."""
+        fl = np.ascontiguousarray(np.asarray(flags, dtype=np.int8))
+        if fl.shape != (self.num_blocks(-1),):
+            raise ValueError("one flag per leaf expected")
+        _check(self._lib.lbm_regrid(self._h, _ptr(fl), len(fl)))
+        lv = ctypes.c_int()
+        _check(self._lib.lbm_num_levels(self._h, ctypes.byref(lv)))
+        self.num_levels = lv.value
 
     def synchronize(self):
         _check(self._lib.lbm_synchronize(self._h))
