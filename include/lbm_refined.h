@@ -163,6 +163,27 @@ int lbm_set_schedule(lbm_forest *f, int schedule);
  * graph.  Results do not depend on it. */
 int lbm_set_launch(lbm_forest *f, int persistent);
 
+/* Launch shape of one level's sweep: persistent as in lbm_set_launch (-1:
+ * follow the forest-wide setting); order 0 sweeps the work tiles in
+ * canonical order, order 1 groups them so that each of the 8 XCDs (to which
+ * workgroups are dispatched round-robin) sweeps one contiguous range of
+ * tiles.  Synchronizes the stream; invalidates captured graphs; kept across
+ * lbm_regrid for levels that still exist.  Results do not depend on it. */
+int lbm_set_level_launch(lbm_forest *f, int level, int persistent, int order);
+int lbm_get_level_launch(const lbm_forest *f, int level, int *persistent, int *order);
+
+/* Autotuner of the launch shape (the batching form: every level's tiles in
+ * one launch per substep, the step captured as a graph).  Times each
+ * candidate (persistent in {0, 1, 2, 4, 8}) x (order in {0, 1}) with
+ * lbm_time_sweeps over one warm-up and n_steps >= 1 coarse steps, keeps for
+ * every level the candidate with the smallest mean step time of that level,
+ * and applies it.  result[3 * L + {0, 1, 2}] = chosen persistent, order and
+ * that level's mean time per level step in ms.  The PDF state is saved
+ * before and restored after (device memory equal to the forest's PDF
+ * storage is allocated for it; LBM_E_OOM otherwise), so the simulation is
+ * left exactly where it was.  Synchronizes. */
+int lbm_autotune(lbm_forest *f, int n_steps, double *result);
+
 /* Dynamic regrid (the paper names dynamic refinement as future work; the
  * operators are its own).  flags[i] for the i-th leaf in canonical order:
  * > 0 split it (if below the max_level given at creation), < 0 merge it with
@@ -194,6 +215,65 @@ int lbm_set_pdfs(lbm_forest *f, const double *h);
 
 /* The D3Q19 velocity set used for raw PDF I/O: e[19][3], w[19]. */
 int lbm_lattice(int32_t *e, double *w);
+
+/* ---- refinement indicators and the learned surrogate ------------------------
+ * The paper leaves the refinement criterion to the user (section 3.3); the
+ * definitions below are this library's.  Per block, on the stored
+ * (post-collision) state: I_omega = max over cells of |curl u| with
+ * block-local differences in the block's lattice units; I_neq = mean over
+ * cells of ||f - f_eq|| / rho.  A block is refine-worthy if I_omega >
+ * theta_omega or I_neq > theta_neq, coarsen-worthy if both are below half
+ * their threshold, kept otherwise. */
+
+/* Per block in canonical order: features[nblocks][12] = { level / Lmax,
+ * 1e3 mean(rho - 1), log10(x + 1e-12) of: std rho, |mean u|,
+ * rms |u - mean u|, max |u|, octant-mean jumps of u along x, y, z, |curl| of
+ * the 2x2x2 octant-mean field, mean neq, max neq } and
+ * crit[nblocks][2] = { I_omega, I_neq }.  Host FP64 outputs; synchronizes. */
+int lbm_block_indicators(lbm_forest *f, double *features, double *crit);
+
+/* The same features[nblocks][12] from one fused pass over the PDFs (no
+ * per-cell intermediates, no curl stencil): the MLP's input path. */
+int lbm_block_features(lbm_forest *f, double *features);
+
+/* Soft targets of the criterion for given crit[n][2]: 1 refine-worthy,
+ * 0 coarsen-worthy, 0.5 keep (host computation). */
+int lbm_plain_targets(const double *crit, int64_t n, double theta_omega, double theta_neq, double *target);
+
+/* MLP 12 -> 64 -> 64 -> 1 (ReLU, sigmoid), FP32 on the device, trained with
+ * the library's own forward, backward and Adam kernels on the mean binary
+ * cross entropy against soft targets (1 refine, 0.5 keep, 0 coarsen).
+ * Parameters packed W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3
+ * (5057 floats).  Inputs are normalized as (x - mean) / std. */
+typedef struct lbm_mlp lbm_mlp;
+int lbm_mlp_create(int device, uint64_t seed, lbm_mlp **out);   /* He init from seed */
+int lbm_mlp_destroy(lbm_mlp *m);
+int lbm_mlp_num_params(int *n);
+int lbm_mlp_get_params(lbm_mlp *m, float *params);
+int lbm_mlp_set_params(lbm_mlp *m, const float *params);        /* resets Adam state */
+/* mean, std: [12]; fmin, fmax: [12] training range (NULL = unbounded); a
+ * feature outside it sends the decision to the criterion. */
+int lbm_mlp_set_normalization(lbm_mlp *m, const double *mean, const double *std, const double *fmin,
+                              const double *fmax);
+/* mean, std (floor 1e-6), min and max of the features X[n][12]. */
+int lbm_mlp_fit_normalization(lbm_mlp *m, const double *X, int64_t n);
+int lbm_mlp_predict(lbm_mlp *m, const double *X, int64_t n, float *prob);        /* X[n][12] */
+int lbm_mlp_gradient(lbm_mlp *m, const double *X, const double *target, int64_t n, float *grad);
+/* Adam (beta 0.9, 0.999), shuffled minibatches of `batch` samples (a
+ * trailing partial batch is skipped), epoch_loss[epochs] (may be NULL). */
+int lbm_mlp_train(lbm_mlp *m, const double *X, const double *target, int64_t n, int epochs, int batch, double lr,
+                  uint64_t seed, double *epoch_loss);
+
+/* Regrid flags (for lbm_regrid) per block in canonical order: +1 refine,
+ * -1 coarsen, 0 keep (refine only below max_level, coarsen only above
+ * level 0).  With m == NULL the criterion decides (two passes over the
+ * cells: moments, then the curl stencil); otherwise the features come from a
+ * single fused pass, the MLP decides (p > 0.75 refine, p < 0.25 coarsen),
+ * and the criterion is evaluated only for blocks where p lies within delta
+ * of 0.25 or 0.75 or a feature is outside the training range;
+ * *n_fallback (may be NULL) counts those blocks. */
+int lbm_refinement_flags(lbm_forest *f, lbm_mlp *m, double theta_omega, double theta_neq, double delta,
+                         int8_t *flags, int32_t *n_fallback);
 
 /* Message of the calling thread's last error ("" if none). */
 const char *lbm_last_error(void);

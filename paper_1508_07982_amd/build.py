@@ -18,7 +18,7 @@ LIB = os.path.join(LIBDIR, "liblbm_refined.so")
 BUILD = os.path.join(ROOT, "_build")
 
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["forest.cpp", "kernels.hip", "sweep_f64.hip", "sweep_f32.hip", "sweep_f16.hip", "api.hip"]
+SOURCES = ["forest.cpp", "kernels.hip", "sweep_f64.hip", "sweep_f32.hip", "sweep_f16.hip", "api.hip", "indicator.hip"]
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 ops are not emitted: some of their forms have given wrong
@@ -35,13 +35,23 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
+def _newest_header() -> float:
+    return max(os.path.getmtime(os.path.join(CSRC, f)) for f in os.listdir(CSRC) if f.endswith(".hpp"))
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (or, with incremental=True, only those whose
+    object is older than the source or any header) and link the library."""
     os.makedirs(LIBDIR, exist_ok=True)
     os.makedirs(BUILD, exist_ok=True)
     objs, procs = [], []
+    hdr = _newest_header()
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD, src + ".o")
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(path), hdr):
+            objs.append(obj)
+            continue
         if src.endswith(".cpp"):
             cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", path, "-o", obj]
         else:
@@ -63,4 +73,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -30,6 +30,7 @@
 #include "../../include/lbm_refined.h"
 #include "forest.hpp"
 #include "kernels.hpp"
+#include "state.hpp"
 
 using namespace lbm;
 
@@ -47,6 +48,22 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+namespace lbm {
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+}  // namespace lbm
+
+namespace {
+
 #define HIP_TRY(expr)                                                                        \
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \
@@ -56,62 +73,7 @@ int fail(int code, const char* fmt, ...) {
     }                                                                                        \
   } while (0)
 
-size_t storage_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
-
-struct LevelDev {
-  int64_t ncells = 0;  // interior cells
-  uint64_t plane = 0;  // elements per direction plane: blocks * n^3
-  int nblocks = 0, nwork = 0, tiles_per_block = 0;
-  int nbuf = 0;
-  void* buf[3] = {nullptr, nullptr, nullptr};
-  int32_t* nbr = nullptr;
-  uint32_t* flags = nullptr;
-  int32_t* fine_index = nullptr;
-  int32_t* fine_nbr = nullptr;
-  int32_t* work = nullptr;
-  double omega = 0.0;
-  std::vector<void*> allocs;  // device memory owned by this level
-};
-
-struct Op {
-  int level;
-  SweepArgs args;
-};
-
 }  // namespace
-
-struct lbm_forest {
-  Forest forest;
-  std::vector<LevelTables> tabs;
-  std::vector<LevelDev> lv;
-  int storage = LBM_F32;
-  int n = 16;
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int schedule = LBM_SCHED_GRAPH;
-  int persistent = 0;
-  int num_cu = 256;
-  bool omega_set = false;
-  std::vector<int> rot;       // per level: buffer holding the current state
-  std::vector<int> rot_prev;  // the same at the start of the last coarse step
-  int64_t steps_since_state = 0;  // coarse steps since the state was set (init, set_pdfs, regrid)
-  int max_level = 0;              // deepest level a regrid may create
-  double omega0 = 0.0;
-  std::map<std::vector<int>, hipGraphExec_t> graphs;
-  int* d_err = nullptr;
-  double* d_partials = nullptr;
-  std::vector<void*> allocations;
-
-  ~lbm_forest() {
-    (void)hipSetDevice(device);
-    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
-    for (void* p : allocations) (void)hipFree(p);
-    for (auto& v : lv)
-      for (void* p : v.allocs) (void)hipFree(p);
-    if (own_stream && stream) (void)hipStreamDestroy(stream);
-  }
-};
 
 namespace {
 
@@ -227,7 +189,7 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   a.plane = d.plane;
   a.plane_par = L > 0 ? f->lv[L - 1].plane : 0;
   a.plane_fine = L + 1 < nlev ? f->lv[L + 1].plane : 0;
-  a.work = d.work;
+  a.work = d.order == 1 && d.work_xcd ? d.work_xcd : d.work;
   a.nwork = d.nwork;
   a.substep = substep;
   a.collide = 1;
@@ -245,21 +207,45 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
     r[L] = (r[L] + 2) % 3;
 }
 
-int grid_for(const lbm_forest* f, int nwork) {
-  if (f->persistent <= 0) return nwork;
-  return std::max(1, std::min(nwork, f->num_cu * f->persistent));
+int grid_for(const lbm_forest* f, int level, int nwork) {
+  const int p = f->lv[level].persistent >= 0 ? f->lv[level].persistent : f->persistent;
+  if (p <= 0) return nwork;
+  return std::max(1, std::min(nwork, f->num_cu * p));
+}
+
+// Tile order 1: workgroups are dispatched round-robin over the 8 XCDs
+// (workgroup w to XCD w % 8, also for a persistent grid, whose size is a
+// multiple of 8), so entry w of the list takes canonical tile
+// start[w % 8] + w / 8 and each XCD sweeps one contiguous range of tiles,
+// keeping the halo planes that neighbouring tiles share in its own L2.
+constexpr int kXcds = 8;
+
+std::vector<int32_t> xcd_grouped(const std::vector<int32_t>& canon) {
+  const int64_t n = int64_t(canon.size());
+  std::vector<int64_t> start(kXcds + 1, 0);
+  for (int x = 0; x < kXcds; ++x) start[x + 1] = start[x] + (n - x + kXcds - 1) / kXcds;
+  std::vector<int32_t> out(canon.size());
+  for (int64_t w = 0; w < n; ++w) out[w] = canon[start[w % kXcds] + w / kXcds];
+  return out;
+}
+
+// Apply level L's tile order (uploads the grouped list when first needed).
+int apply_order(lbm_forest* f, int L) {
+  LevelDev& v = f->lv[L];
+  if (v.order != 1 || v.work_xcd || v.nwork == 0) return LBM_OK;
+  return upload(v.allocs, &v.work_xcd, xcd_grouped(f->tabs[L].work));
 }
 
 int run_ops(lbm_forest* f, const std::vector<Op>& ops, bool per_block) {
   for (const Op& op : ops) {
     if (op.args.nwork <= 0) continue;
     if (!per_block) {
-      HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.args.nwork), f->stream));
+      HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.level, op.args.nwork), f->stream));
     } else {
       const LevelDev& d = f->lv[op.level];
       for (int s = 0; s < d.nblocks; ++s) {
         SweepArgs a = op.args;
-        a.work = op.args.work + size_t(s) * d.tiles_per_block;
+        a.work = d.work + size_t(s) * d.tiles_per_block;
         a.nwork = d.tiles_per_block;
         HIP_TRY(launch_sweep(f->storage, f->n, a, a.nwork, f->stream));
       }
@@ -566,6 +552,105 @@ int lbm_set_launch(lbm_forest* f, int persistent) {
   return LBM_OK;
 }
 
+int lbm_set_level_launch(lbm_forest* f, int level, int persistent, int order) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  if (level < 0 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
+  if (persistent < -1 || persistent > 64) return fail(LBM_E_INVALID, "persistent must lie in [-1, 64]");
+  if (order != 0 && order != 1) return fail(LBM_E_INVALID, "order must be 0 or 1");
+  HIP_TRY(hipSetDevice(f->device));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  f->lv[level].persistent = persistent;
+  f->lv[level].order = order;
+  int rc = apply_order(f, level);
+  if (rc) return rc;
+  invalidate_graphs(f);
+  return LBM_OK;
+}
+
+int lbm_get_level_launch(const lbm_forest* f, int level, int* persistent, int* order) {
+  if (!f || !persistent || !order) return fail(LBM_E_INVALID, "null pointer");
+  if (level < 0 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
+  *persistent = f->lv[level].persistent;
+  *order = f->lv[level].order;
+  return LBM_OK;
+}
+
+int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
+  if (!f || !result) return fail(LBM_E_INVALID, "null pointer");
+  if (n_steps < 1) return fail(LBM_E_INVALID, "n_steps < 1");
+  if (!f->omega_set) return fail(LBM_E_STATE, "lbm_set_level_omega must be called first");
+  HIP_TRY(hipSetDevice(f->device));
+  const int nl = int(f->lv.size());
+  const size_t sb = storage_bytes(f->storage);
+  // the tuning steps advance the state: keep every buffer and restore it
+  std::vector<void*> saved;
+  auto cleanup = [&]() {
+    for (void* p : saved) (void)hipFree(p);
+  };
+  const std::vector<int> rot = f->rot, rot_prev = f->rot_prev;
+  const int64_t since = f->steps_since_state;
+  auto body = [&]() -> int {
+    int rc;
+    for (int L = 0; L < nl; ++L) {
+      const LevelDev& v = f->lv[L];
+      const size_t bytes = size_t(v.plane) * 19 * sb;
+      for (int b = 0; b < v.nbuf; ++b) {
+        uint8_t* p = nullptr;
+        if ((rc = dev_alloc(saved, &p, bytes))) return rc;
+        if (bytes) HIP_TRY(hipMemcpyAsync(p, v.buf[b], bytes, hipMemcpyDeviceToDevice, f->stream));
+      }
+    }
+    static const int kCand[][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {4, 0}, {4, 1}, {8, 0}, {8, 1}};
+    const int ncand = int(sizeof(kCand) / sizeof(kCand[0]));
+    std::vector<double> best(nl, 1e300);
+    std::vector<int> bp(nl, 0), bo(nl, 0);
+    std::vector<double> ms(2 * nl);
+    std::vector<int64_t> cnt(2 * nl);
+    for (int c = 0; c < ncand; ++c) {
+      for (int L = 0; L < nl; ++L) {
+        f->lv[L].persistent = kCand[c][0];
+        f->lv[L].order = kCand[c][1];
+        if ((rc = apply_order(f, L))) return rc;
+      }
+      if ((rc = lbm_time_sweeps(f, 1, ms.data(), cnt.data()))) return rc;  // warm-up
+      if ((rc = lbm_time_sweeps(f, n_steps, ms.data(), cnt.data()))) return rc;
+      for (int L = 0; L < nl; ++L) {
+        // mean time of one step of level L: its substeps' mean launch durations
+        const double t = ms[2 * L] + (L > 0 ? ms[2 * L + 1] : 0.0);
+        if (f->lv[L].nwork > 0 && t < best[L]) {
+          best[L] = t;
+          bp[L] = kCand[c][0];
+          bo[L] = kCand[c][1];
+        }
+      }
+    }
+    for (int L = 0; L < nl; ++L) {
+      f->lv[L].persistent = bp[L];
+      f->lv[L].order = bo[L];
+      if ((rc = apply_order(f, L))) return rc;
+      result[3 * L] = bp[L];
+      result[3 * L + 1] = bo[L];
+      result[3 * L + 2] = best[L] < 1e300 ? best[L] : 0.0;
+    }
+    size_t k = 0;
+    for (int L = 0; L < nl; ++L) {
+      const LevelDev& v = f->lv[L];
+      const size_t bytes = size_t(v.plane) * 19 * sb;
+      for (int b = 0; b < v.nbuf; ++b, ++k)
+        if (bytes) HIP_TRY(hipMemcpyAsync(v.buf[b], saved[k], bytes, hipMemcpyDeviceToDevice, f->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    return LBM_OK;
+  };
+  int rc = body();
+  f->rot = rot;
+  f->rot_prev = rot_prev;
+  f->steps_since_state = since;
+  invalidate_graphs(f);
+  cleanup();
+  return rc;
+}
+
 int lbm_step_coarse(lbm_forest* f, int n_steps) {
   if (!f) return fail(LBM_E_INVALID, "null pointer");
   if (n_steps < 0) return fail(LBM_E_INVALID, "n_steps < 0");
@@ -622,7 +707,7 @@ int lbm_time_sweeps(lbm_forest* f, int n_steps, double* ms, int64_t* launches) {
         HIP_TRY(hipEventCreate(&e1));
         ends.push_back(e1);
         HIP_TRY(hipEventRecord(e0, f->stream));
-        HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.args.nwork), f->stream));
+        HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.level, op.args.nwork), f->stream));
         HIP_TRY(hipEventRecord(e1, f->stream));
       }
       f->rot = r;
@@ -801,6 +886,10 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
       return fail(LBM_E_HIP, "regrid: %s", hipGetErrorString(e));
     }
     invalidate_graphs(f);
+    for (size_t L = 0; L < nlv.size() && L < f->lv.size(); ++L) {
+      nlv[L].persistent = f->lv[L].persistent;
+      nlv[L].order = f->lv[L].order;
+    }
     free_levels(f->lv);
     f->lv = std::move(nlv);
     f->tabs = std::move(ntabs);
@@ -809,6 +898,8 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
     f->rot_prev = f->rot;
     f->steps_since_state = 0;
     set_level_omegas(f);
+    for (int L = 0; L < int(f->lv.size()); ++L)
+      if ((rc2 = apply_order(f, L))) return rc2;
     return LBM_OK;
   };
   rc = body();

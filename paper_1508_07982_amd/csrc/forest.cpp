@@ -373,19 +373,26 @@ int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>
 
   // coalesced (cell, direction) pairs, for reporting only: (X, a) is
   // coalesced if X - e_a, or for an edge direction one of its two axis
-  // projections, lies in region(L+1)
+  // projections, lies in region(L+1).  Whether X - e_a leaves the block
+  // along an axis depends only on whether X sits on the low face, inside
+  // or on the high face along that axis, so cells are counted in those
+  // 27 position classes.
   for (int L = 0; L + 1 < nlev; ++L) {
     LevelTables& t = out[L];
     int64_t pairs = 0;
+    auto class_cells = [n](int c) -> int64_t { return c == 1 ? (n - 2) : 1; };  // 0 low, 1 inside, 2 high
     for (int s = 0; s < t.nblocks; ++s) {
       if (!(t.flags[s] & kHasFine)) continue;
-      for (int c = 0; c < n3; ++c) {
-        const int ijk[3] = {c % n, (c / n) % n, c / (n * n)};
+      for (int cls = 0; cls < 27; ++cls) {
+        const int pc[3] = {cls % 3, (cls / 3) % 3, cls / 9};
+        const int64_t cells = class_cells(pc[0]) * class_cells(pc[1]) * class_cells(pc[2]);
+        if (!cells) continue;
+        int64_t dirs = 0;
         for (int a = 1; a < 19; ++a) {
           int o[3];
           for (int ax = 0; ax < 3; ++ax) {
-            const int sc = ijk[ax] - kE[a][ax];
-            o[ax] = sc < 0 ? -1 : (sc >= n ? 1 : 0);
+            const int e = kE[a][ax];
+            o[ax] = (pc[ax] == 0 && e > 0) ? -1 : ((pc[ax] == 2 && e < 0) ? 1 : 0);
           }
           bool coal = false;
           for (int mask = 1; mask < 8 && !coal; ++mask) {
@@ -399,8 +406,9 @@ int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>
             const int di = (d[0] + 1) + 3 * (d[1] + 1) + 9 * (d[2] + 1);
             if (di != kNbrSelf && t.nbr[size_t(s) * 27 + di] == kNbrFine) coal = true;
           }
-          pairs += coal;
+          dirs += coal;
         }
+        pairs += dirs * cells;
       }
     }
     t.coalesced_pairs = pairs;

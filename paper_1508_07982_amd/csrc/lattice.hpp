@@ -7,6 +7,8 @@
 
 #include <cstdint>
 
+#include "kernels.hpp"
+
 namespace lbm {
 namespace dev {
 

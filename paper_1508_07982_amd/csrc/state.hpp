@@ -1,0 +1,87 @@
+// Internal state of a forest handle, shared by the library's C ABI units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <vector>
+
+#include "../../include/lbm_refined.h"
+#include "forest.hpp"
+#include "kernels.hpp"
+
+namespace lbm {
+
+inline size_t storage_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
+
+
+struct LevelDev {
+  int64_t ncells = 0;  // interior cells
+  uint64_t plane = 0;  // elements per direction plane: blocks * n^3
+  int nblocks = 0, nwork = 0, tiles_per_block = 0;
+  int nbuf = 0;
+  void* buf[3] = {nullptr, nullptr, nullptr};
+  int32_t* nbr = nullptr;
+  uint32_t* flags = nullptr;
+  int32_t* fine_index = nullptr;
+  int32_t* fine_nbr = nullptr;
+  int32_t* work = nullptr;      // work tiles in canonical order
+  int32_t* work_xcd = nullptr;  // the same tiles in XCD-grouped order (order 1), allocated on demand
+  int persistent = -1;          // launch shape of this level; -1: the forest-wide setting
+  int order = 0;                // 0 canonical tile order, 1 XCD-grouped
+  double omega = 0.0;
+  std::vector<void*> allocs;  // device memory owned by this level
+};
+
+struct Op {
+  int level;
+  SweepArgs args;
+};
+
+}  // namespace lbm
+
+struct lbm_forest {
+  using LevelDev = lbm::LevelDev;
+  using Forest = lbm::Forest;
+  using LevelTables = lbm::LevelTables;
+  Forest forest;
+  std::vector<LevelTables> tabs;
+  std::vector<LevelDev> lv;
+  int storage = LBM_F32;
+  int n = 16;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int schedule = LBM_SCHED_GRAPH;
+  int persistent = 0;
+  int num_cu = 256;
+  bool omega_set = false;
+  std::vector<int> rot;       // per level: buffer holding the current state
+  std::vector<int> rot_prev;  // the same at the start of the last coarse step
+  int64_t steps_since_state = 0;  // coarse steps since the state was set (init, set_pdfs, regrid)
+  int max_level = 0;              // deepest level a regrid may create
+  double omega0 = 0.0;
+  std::map<std::vector<int>, hipGraphExec_t> graphs;
+  int* d_err = nullptr;
+  double* d_partials = nullptr;
+  std::vector<void*> allocations;
+
+  ~lbm_forest() {
+    (void)hipSetDevice(device);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    for (void* p : allocations) (void)hipFree(p);
+    for (auto& v : lv)
+      for (void* p : v.allocs) (void)hipFree(p);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+
+namespace lbm {
+
+inline const void* current_state(const lbm_forest* f, int L) { return f->lv[L].buf[f->rot[L]]; }
+
+// Sets the thread's error message and returns `code`.
+int set_error(int code, const char* fmt, ...);
+
+}  // namespace lbm

@@ -137,15 +137,28 @@ __device__ __forceinline__ typename Form<S>::C special_value(const SweepArgs& a,
   return parent_value<S, N, A>(a, cz, zx & (N - 1), zy & (N - 1), zz & (N - 1));
 }
 
+// Index of direction A among the 10 directions with a nonzero x component.
+constexpr int xdir_index(int A) {
+  int q = 0;
+  for (int b = 0; b < A; ++b) q += ex(b) != 0 ? 1 : 0;
+  return q;
+}
+constexpr int kXDirs = 10;
+
 // Ordinary pull of direction A for the W cells (i0 .. i0+W-1, j, k) of one
-// lane: one vector load of the source row and, for x-shifted directions, a
-// DPP move plus one edge load at the ends of the row.  A source block that is
-// not a level-L block sets `odd` (the address is then replaced by the
-// lane's own, so every load stays inside the buffer).
+// lane, in two phases so that every load of the lane is in flight before
+// the first one is used:
+//   issue_dir: one vector load of the source row into h[A] and, for
+//              x-shifted directions, one element load into edge[] (every
+//              lane loads, so no branch and no wait splits the loads);
+//   shift_dir: the x shift of the row by one cell, a DPP move between
+//              lanes, with the edge element at the end of the row.
+// A source block that is not a level-L block sets `odd` (the address is
+// then replaced by the lane's own, so every load stays inside the buffer).
 template <typename S, int N, int A, bool SIMPLE>
-__device__ __forceinline__ void pull_dir(const SweepArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
-                                         typename Form<S>::C (*h)[Geo<S, N>::W], uint32_t& odd) {
-  using C = typename Form<S>::C;
+__device__ __forceinline__ void issue_dir(const SweepArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
+                                          typename Form<S>::C (*h)[Geo<S, N>::W], typename Form<S>::C* edge,
+                                          uint32_t& odd) {
   constexpr int W = Geo<S, N>::W, N3 = Geo<S, N>::N3;
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
   const int sy = j - EY, sz = k - EZ;
@@ -156,40 +169,59 @@ __device__ __forceinline__ void pull_dir(const SweepArgs& a, const SlotCache& sc
   const int nbm = sc.nbr[dmain];
   if (!SIMPLE) odd |= uint32_t(nbm < 0);
   const S* __restrict__ base = static_cast<const S*>(a.cur) + A * a.plane;
-  const uint32_t bm = uint32_t(SIMPLE || nbm >= 0 ? nbm : slot) * N3 + row;
-  C v[W];
-  Vec<S>::load(base + bm + i0, v);
-  if (EX == 0) {
+  const uint32_t bm = uint32_t(SIMPLE || nbm >= 0 ? nbm : slot) * N3 + row + uint32_t(i0);
+  Vec<S>::load(base + bm, h[A]);
+  if constexpr (EX != 0) {
+    const bool at_end = EX == 1 ? i0 == 0 : i0 == N - W;
+    const int nbx = sc.nbr[dmain - EX];
+    if (!SIMPLE) odd |= uint32_t(at_end && nbx < 0);
+    // the lane at the end of the row reads the neighbour row's end element,
+    // the others the end element of their own source row (in bounds, unused)
+    const int eb = at_end ? (SIMPLE || nbx >= 0 ? nbx : slot) : (SIMPLE || nbm >= 0 ? nbm : slot);
+    edge[xdir_index(A)] = Form<S>::ld(base + uint32_t(eb) * N3 + row + uint32_t(EX == 1 ? N - 1 : 0));
+  }
+}
+
+template <typename S, int N, int A>
+__device__ __forceinline__ void shift_dir(int i0, typename Form<S>::C (*h)[Geo<S, N>::W],
+                                          const typename Form<S>::C* edge) {
+  using C = typename Form<S>::C;
+  constexpr int W = Geo<S, N>::W;
+  constexpr int EX = ex(A);
+  if constexpr (EX == 1) {  // source x - 1
+    const C prev = dpp_move<kDppRowShr1>(h[A][W - 1]);
 #pragma unroll
-    for (int c = 0; c < W; ++c) h[A][c] = v[c];
-  } else if (EX == 1) {  // source x - 1
-    const C prev = dpp_move<kDppRowShr1>(v[W - 1]);
+    for (int c = W - 1; c > 0; --c) h[A][c] = h[A][c - 1];
+    h[A][0] = i0 == 0 ? edge[xdir_index(A)] : prev;
+  } else if constexpr (EX == -1) {  // source x + 1
+    const C next = dpp_move<kDppRowShl1>(h[A][0]);
 #pragma unroll
-    for (int c = W - 1; c > 0; --c) h[A][c] = v[c - 1];
-    h[A][0] = prev;
-    if (i0 == 0) {
-      const int nbx = sc.nbr[dmain - 1];
-      if (!SIMPLE) odd |= uint32_t(nbx < 0);
-      h[A][0] = Form<S>::ld(base + uint32_t(SIMPLE || nbx >= 0 ? nbx : slot) * N3 + row + (N - 1));
-    }
-  } else {  // source x + 1
-    const C next = dpp_move<kDppRowShl1>(v[0]);
-#pragma unroll
-    for (int c = 0; c < W - 1; ++c) h[A][c] = v[c + 1];
-    h[A][W - 1] = next;
-    if (i0 == N - W) {
-      const int nbx = sc.nbr[dmain + 1];
-      if (!SIMPLE) odd |= uint32_t(nbx < 0);
-      h[A][W - 1] = Form<S>::ld(base + uint32_t(SIMPLE || nbx >= 0 ? nbx : slot) * N3 + row);
-    }
+    for (int c = 0; c < W - 1; ++c) h[A][c] = h[A][c + 1];
+    h[A][W - 1] = i0 == N - W ? edge[xdir_index(A)] : next;
   }
 }
 
 template <typename S, int N, bool SIMPLE, int A = 0>
+__device__ __forceinline__ void issue_all(const SweepArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
+                                          typename Form<S>::C (*h)[Geo<S, N>::W], typename Form<S>::C* edge,
+                                          uint32_t& odd) {
+  issue_dir<S, N, A, SIMPLE>(a, sc, slot, i0, j, k, h, edge, odd);
+  if constexpr (A + 1 < 19) issue_all<S, N, SIMPLE, A + 1>(a, sc, slot, i0, j, k, h, edge, odd);
+}
+
+template <typename S, int N, int A = 0>
+__device__ __forceinline__ void shift_all(int i0, typename Form<S>::C (*h)[Geo<S, N>::W],
+                                          const typename Form<S>::C* edge) {
+  shift_dir<S, N, A>(i0, h, edge);
+  if constexpr (A + 1 < 19) shift_all<S, N, A + 1>(i0, h, edge);
+}
+
+template <typename S, int N, bool SIMPLE>
 __device__ __forceinline__ void pull_all(const SweepArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
                                          typename Form<S>::C (*h)[Geo<S, N>::W], uint32_t& odd) {
-  pull_dir<S, N, A, SIMPLE>(a, sc, slot, i0, j, k, h, odd);
-  if constexpr (A + 1 < 19) pull_all<S, N, SIMPLE, A + 1>(a, sc, slot, i0, j, k, h, odd);
+  typename Form<S>::C edge[kXDirs];
+  issue_all<S, N, SIMPLE>(a, sc, slot, i0, j, k, h, edge, odd);
+  shift_all<S, N>(i0, h, edge);
 }
 
 // Cells of a lane whose direction-A source is not an ordinary level-L read:

@@ -73,6 +73,26 @@ _SIGNATURES = {
     "lbm_synchronize": [ctypes.c_void_p],
     "lbm_time_sweeps": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_regrid": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
+    "lbm_block_indicators": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_mlp_create": [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)],
+    "lbm_mlp_destroy": [ctypes.c_void_p],
+    "lbm_mlp_num_params": [ctypes.POINTER(ctypes.c_int)],
+    "lbm_mlp_get_params": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_mlp_set_params": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_mlp_set_normalization": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p],
+    "lbm_mlp_predict": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p],
+    "lbm_mlp_gradient": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p],
+    "lbm_mlp_train": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                      ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p],
+    "lbm_set_level_launch": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+    "lbm_get_level_launch": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_autotune": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
+    "lbm_block_features": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_plain_targets": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_void_p],
+    "lbm_mlp_fit_normalization": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
+    "lbm_refinement_flags": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
     "lbm_get_pdfs": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_pdfs": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_lattice": [ctypes.c_void_p, ctypes.c_void_p],
@@ -268,6 +288,45 @@ class Forest:
         _check(self._lib.lbm_num_levels(self._h, ctypes.byref(lv)))
         self.num_levels = lv.value
 
+    def block_indicators(self):
+        """(features (nblocks, 12), crit (nblocks, 2) = (I_omega, I_neq))."""
+        nb = self.num_blocks(-1)
+        feat = np.zeros((nb, 12))
+        crit = np.zeros((nb, 2))
+        _check(self._lib.lbm_block_indicators(self._h, _ptr(feat), _ptr(crit)))
+        return feat, crit
+
+    def set_level_launch(self, level, persistent, order=0):
+        _check(self._lib.lbm_set_level_launch(self._h, int(level), int(persistent), int(order)))
+
+    def get_level_launch(self, level):
+        p, o = ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.lbm_get_level_launch(self._h, int(level), ctypes.byref(p), ctypes.byref(o)))
+        return p.value, o.value
+
+    def autotune(self, n_steps=2):
+        """Pick each level's launch shape by timing; returns a list of
+        {level, persistent, order, ms_per_level_step}."""
+        res = np.zeros(3 * self.num_levels)
+        _check(self._lib.lbm_autotune(self._h, int(n_steps), _ptr(res)))
+        return [{"level": L, "persistent": int(res[3 * L]), "order": int(res[3 * L + 1]),
+                 "ms_per_level_step": float(res[3 * L + 2])} for L in range(self.num_levels)]
+
+    def block_features(self):
+        """Features (nblocks, 12) from the fused single-pass kernel."""
+        feat = np.zeros((self.num_blocks(-1), 12))
+        _check(self._lib.lbm_block_features(self._h, _ptr(feat)))
+        return feat
+
+    def refinement_flags(self, theta_omega, theta_neq, mlp=None, delta=0.05):
+        """Regrid flags per block from the criterion (mlp None) or the MLP;
+        returns (flags, number of blocks decided by the fallback)."""
+        flags = np.zeros(self.num_blocks(-1), dtype=np.int8)
+        fb = ctypes.c_int32(0)
+        _check(self._lib.lbm_refinement_flags(self._h, mlp._h if mlp is not None else None, float(theta_omega),
+                                              float(theta_neq), float(delta), _ptr(flags), ctypes.byref(fb)))
+        return flags, fb.value
+
     def synchronize(self):
         _check(self._lib.lbm_synchronize(self._h))
 
@@ -294,3 +353,73 @@ class Forest:
         if h.shape != (self.num_cells(-1), 19):
             raise ValueError("expected (num_cells, 19)")
         _check(self._lib.lbm_set_pdfs(self._h, _ptr(h)))
+
+
+def plain_targets(crit, theta_omega, theta_neq) -> np.ndarray:
+    """Soft targets of the criterion: 1 refine-worthy, 0 coarsen-worthy, 0.5 keep."""
+    crit = np.ascontiguousarray(crit, dtype=np.float64).reshape(-1, 2)
+    t = np.zeros(len(crit))
+    _check(load_library().lbm_plain_targets(_ptr(crit), len(crit), float(theta_omega), float(theta_neq), _ptr(t)))
+    return t
+
+
+class MLP:
+    """The refinement surrogate 12 -> 64 -> 64 -> 1 owned by the HIP library."""
+
+    def __init__(self, seed: int = 0, device: int = 0):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        _check(self._lib.lbm_mlp_create(int(device), int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int()
+        _check(self._lib.lbm_mlp_num_params(ctypes.byref(n)))
+        self.num_params = n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbm_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        p = np.zeros(self.num_params, dtype=np.float32)
+        _check(self._lib.lbm_mlp_get_params(self._h, _ptr(p)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(self._lib.lbm_mlp_set_params(self._h, _ptr(p)))
+
+    def set_normalization(self, mean, std, fmin=None, fmax=None):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None for a in (mean, std, fmin, fmax)]
+        _check(self._lib.lbm_mlp_set_normalization(self._h, *[_ptr(a) if a is not None else None for a in arrs]))
+
+    def fit_normalization(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 12)
+        _check(self._lib.lbm_mlp_fit_normalization(self._h, _ptr(X), len(X)))
+
+    def predict(self, X) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 12)
+        p = np.zeros(len(X), dtype=np.float32)
+        _check(self._lib.lbm_mlp_predict(self._h, _ptr(X), len(X), _ptr(p)))
+        return p
+
+    def gradient(self, X, t) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 12)
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        g = np.zeros(self.num_params, dtype=np.float32)
+        _check(self._lib.lbm_mlp_gradient(self._h, _ptr(X), _ptr(t), len(X), _ptr(g)))
+        return g
+
+    def train(self, X, t, epochs=20, batch=256, lr=1e-3, seed=0) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 12)
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        losses = np.zeros(max(epochs, 1))
+        _check(self._lib.lbm_mlp_train(self._h, _ptr(X), _ptr(t), len(X), int(epochs), int(batch), float(lr),
+                                       int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(losses)))
+        return losses[:epochs]

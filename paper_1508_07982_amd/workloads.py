@@ -140,6 +140,33 @@ def config_slab_sphere(n: int = 16, roots: int = 5) -> Workload:
                     "%d^3 roots of %d^3 cells, plate + sphere surface refined to level 3" % (R, n))
 
 
+def vortex_blobs(seed: int = 5, count: int = 4, sigma: float = 0.06):
+    """Seeded blob centres in [0.2, 0.8]^3 and unit rotation axes."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.2, 0.8, (count, 3))
+    axes = rng.normal(size=(count, 3))
+    axes /= np.linalg.norm(axes, axis=1, keepdims=True)
+    return centres, axes, sigma
+
+
+def config_vortices(n: int = 16, roots: int = 4, max_level: int = 4, seed: int = 5) -> Workload:
+    """5 levels (0..4) of 16^3-cell blocks on 4^3 roots, 4 seeded Gaussian
+    vortex blobs of peak velocity 0.05 (sigma = 0.06); the initial forest
+    refines level-l blocks within (3 - 0.5 l) sigma of a blob centre.  The
+    seed places the blobs."""
+    R = roots
+    centres, axes, sigma = vortex_blobs(seed)
+    shifts = np.array(np.meshgrid([-1, 0, 1], [-1, 0, 1], [-1, 0, 1])).T.reshape(-1, 3)
+    images = (centres[:, None, :] + shifts[None, :, :]).reshape(-1, 3)  # all periodic images
+
+    def refine(level, x, y, z):
+        lo, hi = _box(R, level, x, y, z)
+        d = np.maximum(np.maximum(lo[None, :] - images, images - hi[None, :]), 0.0)
+        return bool(np.any(np.sqrt((d * d).sum(1)) < (3.0 - 0.5 * level) * sigma))
+    return Workload("vortices_n%d_R%d_L%d_s%d" % (n, R, max_level, seed), R, n, max_level, 1.9, refine, "vortex_blobs",
+                    0.05, 0.0, seed, 500, "%d^3 roots of %d^3 cells, 4 vortex blobs, levels 0..%d" % (R, n, max_level))
+
+
 # ----------------------------------------------------------------------------
 # initial fields
 # ----------------------------------------------------------------------------
@@ -161,6 +188,20 @@ def cell_centres(leaves, R, n):
     return centres, levels, lin
 
 
+def _blob_velocity(xyz, centres, axes, sigma, peak):
+    """Sum of blobs u = peak sqrt(e) (a x r) / sigma exp(-|r|^2 / (2 sigma^2)),
+    r = x - c at the nearest periodic image: divergence-free, speed `peak`
+    at distance sigma from the axis in the blob's mid-plane."""
+    u = np.zeros_like(xyz)
+    for c, a in zip(centres, axes):
+        r = xyz - c
+        r -= np.round(r)
+        ar = np.cross(a[None, :], r)
+        g = np.exp(-(r * r).sum(1) / (2.0 * sigma * sigma))
+        u += peak * math.sqrt(math.e) / sigma * ar * g[:, None]
+    return u
+
+
 def initial_field(w: Workload, leaves):
     """(rho, u) at every cell of `leaves` (given order)."""
     centres, levels, lin = cell_centres(leaves, w.R, w.n)
@@ -171,6 +212,9 @@ def initial_field(w: Workload, leaves):
         u = np.zeros((N, 3))
         u[:, 0] = w.amplitude * np.sin(x) * np.cos(y) * np.cos(z)
         u[:, 1] = -w.amplitude * np.cos(x) * np.sin(y) * np.cos(z)
+    elif w.field == "vortex_blobs":
+        centres_b, axes_b, sigma = vortex_blobs(w.seed)
+        u = _blob_velocity(centres, centres_b, axes_b, sigma, w.amplitude)
     elif w.field == "uniform":
         u = np.tile(np.asarray(w.amplitude, dtype=np.float64).reshape(1, 3), (N, 1))
     else:

@@ -1,0 +1,95 @@
+"""Launch shapes and the autotuner through the C ABI: per-level persistent
+grids and XCD-grouped tile orders give bitwise the same state as the
+default launch, the autotuner leaves the simulation state exactly where it
+was, and per-level settings survive a regrid."""
+
+import numpy as np
+import pytest
+
+from paper_1508_07982_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def spec_three(n):
+    def refine(L, x, y, z):
+        return (L == 0 and (x, y, z) == (1, 1, 1)) or (L == 1 and (x, y, z) == (3, 3, 2))
+    return (3, 3, 3), n, 3, refine
+
+
+def make(storage="f32", n=8, seed=1):
+    R, n, Lmax, refine = spec_three(n)
+    g = lbm.Forest(R, n, Lmax, refine=refine, storage=storage)
+    N = g.num_cells()
+    rng = np.random.default_rng(seed)
+    g.set_level_omega(1.7)
+    g.init_pdfs(1.0 + 0.01 * rng.uniform(-1, 1, N), 0.03 * rng.uniform(-1, 1, (N, 3)))
+    return g
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
+@pytest.mark.parametrize("shape", [[(0, 1), (2, 0), (1, 1)], [(4, 1), (0, 1), (8, 0)], [(-1, 1), (-1, 1), (-1, 1)]])
+def test_level_launch_shapes_bitwise_equal(storage, shape):
+    print(f"level launch {storage} {shape}", flush=True)
+    ref = make(storage)
+    ref.set_schedule("direct")
+    ref.step_coarse(3)
+    want = ref.get_pdfs()
+    ref.close()
+    g = make(storage)
+    for L, (p, o) in enumerate(shape):
+        g.set_level_launch(L, p, o)
+        assert g.get_level_launch(L) == (p, o)
+    g.step_coarse(3)
+    assert np.array_equal(g.get_pdfs(), want)
+    g.close()
+
+
+def test_autotune_restores_state_and_applies_choice():
+    ref = make("f32", seed=4)
+    ref.step_coarse(2)
+    ref.step_coarse(2)
+    want = ref.get_pdfs()
+    ref.close()
+    g = make("f32", seed=4)
+    g.step_coarse(2)
+    res = g.autotune(n_steps=1)
+    assert len(res) == g.num_levels
+    for r in res:
+        assert r["persistent"] in (0, 1, 2, 4, 8) and r["order"] in (0, 1) and r["ms_per_level_step"] > 0
+        assert g.get_level_launch(r["level"]) == (r["persistent"], r["order"])
+    g.step_coarse(2)
+    assert np.array_equal(g.get_pdfs(), want)
+    g.close()
+
+
+def test_level_launch_kept_across_regrid():
+    a = make("f32", seed=5)
+    b = make("f32", seed=5)
+    for L in range(b.num_levels):
+        b.set_level_launch(L, 2, 1)
+    a.step_coarse(1)
+    b.step_coarse(1)
+    rng = np.random.default_rng(9)
+    flags = rng.choice([-1, 0, 1], size=a.num_blocks(), p=[0.4, 0.4, 0.2]).astype(np.int8)
+    nl = b.num_levels
+    a.regrid(flags)
+    b.regrid(flags)
+    for L in range(min(nl, b.num_levels)):
+        assert b.get_level_launch(L) == (2, 1)
+    a.step_coarse(2)
+    b.step_coarse(2)
+    assert np.array_equal(a.get_pdfs(), b.get_pdfs())
+    a.close()
+    b.close()
+
+
+def test_level_launch_rejects_bad_arguments():
+    g = make("f32")
+    with pytest.raises(lbm.LBMError):
+        g.set_level_launch(g.num_levels, 0, 0)
+    with pytest.raises(lbm.LBMError):
+        g.set_level_launch(0, 0, 2)
+    with pytest.raises(lbm.LBMError):
+        g.set_level_launch(0, 65, 0)
+    g.close()
