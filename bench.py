@@ -7,7 +7,8 @@ the surface of a central sphere of radius 0.25 refined at every level up to
 level 3 (121.4 M cells in (0, 352, 984, 2368) blocks), D3Q19 SRT with
 omega_0 = 1.9, Taylor-Green amplitude 0.02 plus seeded noise.  One "step" is
 one coarse time step (Algorithm 1 from level 0: sum_L 2^L N_L = 773 M cell
-updates), FP32 PDFs, whole step captured as a HIP graph; inputs are resident
+updates), FP32 PDFs, whole step captured as a HIP graph with the launch
+shape of every level picked by the library's autotuner; inputs are resident
 in HBM before timing starts.
 
 Prints one JSON line: MLUPS across all levels, the roofline of the dominant
@@ -74,6 +75,19 @@ def timed_steps(torch, g, stream, steps):
     return start.elapsed_time(end) / steps
 
 
+def level_table(g, sweeps, s_bytes):
+    """Mean launch time and algorithmic GB/s of every (level, substep)."""
+    return {f"L{L}s{s}": {"ms": round(m, 4), "launches": c, "cells": g.num_cells(L),
+                          "GBps": round(38 * s_bytes * g.num_cells(L) / (m * 1e-3) / 1e9, 1)}
+            for (L, s), (m, c) in sorted(sweeps.items())}
+
+
+def launch_table(res):
+    """Autotuner choice per level: persistent workgroups per CU (0: one per
+    tile) and tile order (1: grouped by XCD)."""
+    return {f"L{r['level']}": [r["persistent"], r["order"]] for r in res}
+
+
 def cpu_baseline(W, budget_s: float = 12.0):
     """The FP64 oracle on the same sphere-shell geometry with 8^3-cell
     blocks (1/64 of the cells), timed over as many coarse steps as fit in
@@ -124,6 +138,7 @@ def main():
     g = make_forest(lbm, W, w, "f32", stream.cuda_stream)
     upd = g.updates_per_coarse_step()
     cells = g.num_cells()
+    launch = g.autotune(2)  # per-level launch shape, state restored afterwards
     g.step_coarse(args.warmup)
     M0, _ = g.mass()
     ms = timed_steps(torch, g, stream, args.steps)
@@ -140,9 +155,7 @@ def main():
     alg_bytes = 38 * s_bytes * nf          # 19 PDFs read + 19 written per interior cell
     achieved = alg_bytes / (fin_ms * 1e-3) / 1e9
     traffic = measured_traffic("f32", nf, fin_ms)
-    per_level = {f"L{L}s{s}": {"ms": round(m, 4), "launches": c, "cells": g.num_cells(L),
-                               "GBps": round(38 * s_bytes * g.num_cells(L) / (m * 1e-3) / 1e9, 1)}
-                 for (L, s), (m, c) in sorted(sweeps.items())}
+    per_level = level_table(g, sweeps, s_bytes)
     g.close()
     del g
     torch.cuda.synchronize()
@@ -151,10 +164,15 @@ def main():
                            "roofline_MLUPS": round(HBM_PEAK_GBS * 1e9 / (38 * 4) / 1e6, 1)}}
     if not args.no_forms:
         g16 = make_forest(lbm, W, w, "f16", stream.cuda_stream)
+        launch16 = g16.autotune(2)
         g16.step_coarse(2)
+        M16a, _ = g16.mass()
         ms16 = timed_steps(torch, g16, stream, max(3, args.steps // 2))
+        M16b, _ = g16.mass()
         forms["f16_graph"] = {"MLUPS": round(upd / (ms16 * 1e-3) / 1e6, 1), "ms_per_step": round(ms16, 3),
-                              "roofline_MLUPS": round(HBM_PEAK_GBS * 1e9 / (38 * 2) / 1e6, 1)}
+                              "roofline_MLUPS": round(HBM_PEAK_GBS * 1e9 / (38 * 2) / 1e6, 1),
+                              "per_level": level_table(g16, g16.time_sweeps(2), 2),
+                              "launch": launch_table(launch16), "mass_drift": abs(M16b - M16a) / M16a}
         g16.close()
         del g16
         gp = make_forest(lbm, W, w, "f32", stream.cuda_stream)
@@ -187,6 +205,7 @@ def main():
             "updates_per_coarse_step": upd,
             "omega0": w.omega0,
             "schedule": "hipGraph of the whole coarse step",
+            "launch": launch_table(launch),
             "mass_drift": abs(M1 - M0) / M0,
         },
         "roofline": {

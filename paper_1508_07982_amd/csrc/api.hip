@@ -582,8 +582,10 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
   HIP_TRY(hipSetDevice(f->device));
   const int nl = int(f->lv.size());
   const size_t sb = storage_bytes(f->storage);
-  // the tuning steps advance the state: keep every buffer and restore it
-  std::vector<void*> saved;
+  // the tuning steps advance the state: keep every buffer and restore it;
+  // copy[L][b] is null for a level without cells
+  std::vector<void*> saved;  // owner of the copies
+  std::vector<std::vector<uint8_t*>> copy(nl);
   auto cleanup = [&]() {
     for (void* p : saved) (void)hipFree(p);
   };
@@ -594,10 +596,10 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
     for (int L = 0; L < nl; ++L) {
       const LevelDev& v = f->lv[L];
       const size_t bytes = size_t(v.plane) * 19 * sb;
-      for (int b = 0; b < v.nbuf; ++b) {
-        uint8_t* p = nullptr;
-        if ((rc = dev_alloc(saved, &p, bytes))) return rc;
-        if (bytes) HIP_TRY(hipMemcpyAsync(p, v.buf[b], bytes, hipMemcpyDeviceToDevice, f->stream));
+      copy[L].assign(v.nbuf, nullptr);
+      for (int b = 0; b < v.nbuf && bytes; ++b) {
+        if ((rc = dev_alloc(saved, &copy[L][b], bytes))) return rc;
+        HIP_TRY(hipMemcpyAsync(copy[L][b], v.buf[b], bytes, hipMemcpyDeviceToDevice, f->stream));
       }
     }
     static const int kCand[][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {4, 0}, {4, 1}, {8, 0}, {8, 1}};
@@ -632,12 +634,11 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
       result[3 * L + 1] = bo[L];
       result[3 * L + 2] = best[L] < 1e300 ? best[L] : 0.0;
     }
-    size_t k = 0;
     for (int L = 0; L < nl; ++L) {
       const LevelDev& v = f->lv[L];
       const size_t bytes = size_t(v.plane) * 19 * sb;
-      for (int b = 0; b < v.nbuf; ++b, ++k)
-        if (bytes) HIP_TRY(hipMemcpyAsync(v.buf[b], saved[k], bytes, hipMemcpyDeviceToDevice, f->stream));
+      for (int b = 0; b < v.nbuf; ++b)
+        if (copy[L][b]) HIP_TRY(hipMemcpyAsync(v.buf[b], copy[L][b], bytes, hipMemcpyDeviceToDevice, f->stream));
     }
     HIP_TRY(hipStreamSynchronize(f->stream));
     return LBM_OK;

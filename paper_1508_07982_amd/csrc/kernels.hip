@@ -197,7 +197,7 @@ inline unsigned grid_for(int64_t n, int threads) { return unsigned((n + threads 
 
 int sweep_tile_cells(int storage, int n) {
   const int n3 = n * n * n;
-  const int w = storage == 0 ? Vec<double>::W : Vec<float>::W;
+  const int w = storage == 0 ? Vec<double>::W : (storage == 2 && n >= 8 ? 8 : Vec<float>::W);
   return n3 < 256 * w ? n3 : 256 * w;
 }
 

@@ -58,6 +58,7 @@ struct Form<__half> {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename S>
 struct Vec;
@@ -121,9 +122,13 @@ __device__ __forceinline__ double dpp_move(double v) {
   return __longlong_as_double((long long)(uint32_t(lo)) | ((long long)hi << 32));
 }
 
+// Cells per lane: FP16 blocks of 8 or more cells per row keep 8 cells per
+// lane as packed pairs (16-byte accesses, see the packed path of the sweep);
+// otherwise the storage form's vector width.
 template <typename S, int N>
 struct Geo {
-  static constexpr int W = Vec<S>::W;
+  static constexpr bool PACKED = sizeof(S) == 2 && N >= 8;
+  static constexpr int W = PACKED ? 8 : Vec<S>::W;
   static constexpr int N3 = N * N * N;
   static constexpr int CELLS = N3 < 256 * W ? N3 : 256 * W;  // cells per work tile
   static constexpr int T = CELLS / W;                          // threads per workgroup

@@ -311,6 +311,143 @@ __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache&
   for (int d = 0; d < 19; ++d) Vec<S>::store(nxt + d * a.plane, h[d]);
 }
 
+// ---- packed FP16 path: 8 cells per lane as 4 registers of half pairs ------
+//
+// Register q of direction A holds cells 2q (low half) and 2q + 1 (high
+// half) of the lane's row segment.  The x shift by one cell is a funnel
+// shift of neighbouring pairs by 16 bits (the pair across the lane
+// boundary comes from a DPP move or from the edge element), so the pulled
+// values stay packed; each pair is unpacked to FP32 only for its collision.
+// Special sources (coalescence, explosion) are evaluated in FP32 and
+// stored into the packed row rounded to FP16, as a ghost layer in FP16
+// storage would hold them.
+__device__ __forceinline__ float half_lo(uint32_t q) { return __half2float(__ushort_as_half(uint16_t(q & 0xFFFFu))); }
+__device__ __forceinline__ float half_hi(uint32_t q) { return __half2float(__ushort_as_half(uint16_t(q >> 16))); }
+__device__ __forceinline__ uint32_t half_bits(float v) { return uint32_t(__half_as_ushort(__float2half_rn(v))); }
+__device__ __forceinline__ uint32_t pack_pair(float lo, float hi) { return half_bits(lo) | (half_bits(hi) << 16); }
+// (hi:lo) >> 16: the high half of lo and the low half of hi
+__device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) { return __builtin_amdgcn_alignbit(hi, lo, 16); }
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_move_u32(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, 0xF, 0xF, true));
+}
+
+template <int N, int A, bool SIMPLE>
+__device__ __forceinline__ void issue_dir_h8(const SweepArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
+                                             uint32_t (*q)[4], uint32_t* edge, uint32_t& odd) {
+  constexpr int N3 = N * N * N;
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  const int sy = j - EY, sz = k - EZ;
+  const int oy = EY == 0 ? 0 : side<N>(sy);
+  const int oz = EZ == 0 ? 0 : side<N>(sz);
+  const uint32_t row = uint32_t(N * ((sy & (N - 1)) + N * (sz & (N - 1))));
+  const int dmain = 13 + 3 * oy + 9 * oz;
+  const int nbm = sc.nbr[dmain];
+  if (!SIMPLE) odd |= uint32_t(nbm < 0);
+  const uint16_t* __restrict__ base = static_cast<const uint16_t*>(a.cur) + A * a.plane;
+  const int bms = SIMPLE || nbm >= 0 ? nbm : slot;
+  const uint4 v = *reinterpret_cast<const uint4*>(base + uint32_t(bms) * N3 + row + uint32_t(i0));
+  q[A][0] = v.x, q[A][1] = v.y, q[A][2] = v.z, q[A][3] = v.w;
+  if constexpr (EX != 0) {
+    const bool at_end = EX == 1 ? i0 == 0 : i0 == N - 8;
+    const int nbx = sc.nbr[dmain - EX];
+    if (!SIMPLE) odd |= uint32_t(at_end && nbx < 0);
+    const int eb = at_end ? (SIMPLE || nbx >= 0 ? nbx : slot) : bms;
+    edge[xdir_index(A)] = base[uint32_t(eb) * N3 + row + uint32_t(EX == 1 ? N - 1 : 0)];
+  }
+}
+
+template <int N, int A>
+__device__ __forceinline__ void shift_dir_h8(int i0, uint32_t (*q)[4], const uint32_t* edge) {
+  constexpr int EX = ex(A);
+  if constexpr (EX == 1) {  // cell c takes cell c - 1
+    const uint32_t prev = dpp_move_u32<kDppRowShr1>(q[A][3]);
+    const uint32_t in = i0 == 0 ? edge[xdir_index(A)] << 16 : prev;
+    q[A][3] = funnel16(q[A][3], q[A][2]);
+    q[A][2] = funnel16(q[A][2], q[A][1]);
+    q[A][1] = funnel16(q[A][1], q[A][0]);
+    q[A][0] = funnel16(q[A][0], in);
+  } else if constexpr (EX == -1) {  // cell c takes cell c + 1
+    const uint32_t next = dpp_move_u32<kDppRowShl1>(q[A][0]);
+    const uint32_t in = i0 == N - 8 ? edge[xdir_index(A)] : next;
+    q[A][0] = funnel16(q[A][1], q[A][0]);
+    q[A][1] = funnel16(q[A][2], q[A][1]);
+    q[A][2] = funnel16(q[A][3], q[A][2]);
+    q[A][3] = funnel16(in, q[A][3]);
+  }
+}
+
+template <int N, bool SIMPLE, int A = 0>
+__device__ __forceinline__ void issue_all_h8(const SweepArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
+                                             uint32_t (*q)[4], uint32_t* edge, uint32_t& odd) {
+  issue_dir_h8<N, A, SIMPLE>(a, sc, slot, i0, j, k, q, edge, odd);
+  if constexpr (A + 1 < 19) issue_all_h8<N, SIMPLE, A + 1>(a, sc, slot, i0, j, k, q, edge, odd);
+}
+
+template <int N, int A = 0>
+__device__ __forceinline__ void shift_all_h8(int i0, uint32_t (*q)[4], const uint32_t* edge) {
+  shift_dir_h8<N, A>(i0, q, edge);
+  if constexpr (A + 1 < 19) shift_all_h8<N, A + 1>(i0, q, edge);
+}
+
+template <int N, int A = 0>
+__device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl, int i0,
+                                          int j, int k, uint32_t (*q)[4]) {
+  uint32_t co;
+  const uint32_t spec = special_cells<N, 8, A>(sc, fl, i0, j, k, co);
+  if (spec) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if ((spec >> c) & 1u) {
+        uint32_t& w = q[A][c >> 1];
+        const float regular = c & 1 ? half_hi(w) : half_lo(w);
+        const float v = special_value<__half, N, A>(a, sc, slot, i0 + c, j, k, (co >> c) & 1u, regular);
+        w = c & 1 ? ((w & 0xFFFFu) | (half_bits(v) << 16)) : ((w & 0xFFFF0000u) | half_bits(v));
+      }
+  }
+  if constexpr (A + 1 < 19) fixups_h8<N, A + 1>(a, sc, slot, fl, i0, j, k, q);
+}
+
+template <int N, bool SIMPLE>
+__device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl,
+                                               int cell0) {
+  constexpr int N3 = N * N * N;
+  const int i0 = cell0 & (N - 1), j = (cell0 / N) & (N - 1), k = cell0 / (N * N);
+  uint32_t q[19][4];
+  uint32_t edge[kXDirs];
+  uint32_t odd = 0;
+  issue_all_h8<N, SIMPLE>(a, sc, slot, i0, j, k, q, edge, odd);
+  shift_all_h8<N>(i0, q, edge);
+  if (!SIMPLE && odd) fixups_h8<N>(a, sc, slot, fl, i0, j, k, q);
+  if (a.collide) {
+    const float om = a.omega;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      float h[19][2];
+#pragma unroll
+      for (int d = 0; d < 19; ++d) h[d][0] = half_lo(q[d][p]), h[d][1] = half_hi(q[d][p]);
+      collide<float, 2>(h, 0, om);
+      collide<float, 2>(h, 1, om);
+#pragma unroll
+      for (int d = 0; d < 19; ++d) q[d][p] = pack_pair(h[d][0], h[d][1]);
+    }
+  }
+  uint16_t* __restrict__ nxt = static_cast<uint16_t*>(a.nxt) + uint32_t(slot) * N3 + uint32_t(cell0);
+#pragma unroll
+  for (int d = 0; d < 19; ++d) {
+    const u32x4 t = {q[d][0], q[d][1], q[d][2], q[d][3]};
+    __builtin_nontemporal_store(t, reinterpret_cast<u32x4*>(nxt + d * a.plane));
+  }
+}
+
+template <typename S, int N, bool SIMPLE>
+__device__ __forceinline__ void update_any(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl, int cell0) {
+  if constexpr (Geo<S, N>::PACKED)
+    update_lane_h8<N, SIMPLE>(a, sc, slot, fl, cell0);
+  else
+    update_lane<S, N, SIMPLE>(a, sc, slot, fl, cell0);
+}
+
 template <typename S, int N>
 __device__ __forceinline__ void sweep_item(const SweepArgs& a, SlotCache& sc, int w) {
   constexpr int W = Geo<S, N>::W, CELLS = Geo<S, N>::CELLS, TPB = Geo<S, N>::TPB;
@@ -321,9 +458,9 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, SlotCache& sc, in
   __syncthreads();
   const uint32_t fl = a.flags[slot];
   if (fl & kAllSameLevel)
-    update_lane<S, N, true>(a, sc, slot, fl, cell0);
+    update_any<S, N, true>(a, sc, slot, fl, cell0);
   else
-    update_lane<S, N, false>(a, sc, slot, fl, cell0);
+    update_any<S, N, false>(a, sc, slot, fl, cell0);
 }
 
 // One workgroup per work tile (PERSIST = false), or a fixed grid of

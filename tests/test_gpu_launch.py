@@ -63,6 +63,30 @@ def test_autotune_restores_state_and_applies_choice():
     g.close()
 
 
+def test_autotune_with_empty_level():
+    # level 0 holds no blocks: the 2:1 balance splits every root
+    def refine(L, x, y, z):
+        return L == 0 or (L == 1 and (x, y, z) == (1, 1, 0))
+    want = None
+    for tune in (False, True):
+        g = lbm.Forest((2, 2, 2), 8, 2, refine=refine, storage="f32")
+        assert g.num_cells(0) == 0
+        N = g.num_cells()
+        rng = np.random.default_rng(6)
+        g.set_level_omega(1.6)
+        g.init_pdfs(1.0 + 0.01 * rng.uniform(-1, 1, N), 0.03 * rng.uniform(-1, 1, (N, 3)))
+        g.step_coarse(1)
+        if tune:
+            res = g.autotune(n_steps=1)
+            assert res[0]["ms_per_level_step"] == 0.0
+        g.step_coarse(2)
+        if want is None:
+            want = g.get_pdfs()
+        else:
+            assert np.array_equal(g.get_pdfs(), want)
+        g.close()
+
+
 def test_level_launch_kept_across_regrid():
     a = make("f32", seed=5)
     b = make("f32", seed=5)
