@@ -7,10 +7,15 @@
             --command "..."
 
 The sweep workload is the benchmark grid (sphere shell, 4^3 roots of 32^3
-cells, 121.4 M cells) stepped with one launch per level substep, so every
-sweep dispatch shows up in the trace.  FETCH_SIZE and WRITE_SIZE (KiB per
-dispatch) are scaled by what the same counters read for a copy of a known
-byte count; the result is the HBM traffic of one finest-level sweep launch.
+cells, 121.4 M cells) with the launch shape chosen by the autotuner, as in
+bench.py, stepped with one launch per level substep, so every sweep dispatch
+shows up in the trace.  FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are
+scaled by what the same counters read for a copy of a known byte count; the
+result is the HBM traffic of one finest-level sweep launch.
+
+Both workloads run the autotuner first and then a mass reduction; only
+sweep dispatches after the first reduction kernel (the measured phase) enter
+the per-level figures.
 """
 
 from __future__ import annotations
@@ -57,6 +62,9 @@ def run_sweep(storage: str, steps: int):
     g.set_schedule("direct")
     g.init_pdfs(rho, u)
     del rho, u
+    launch = g.autotune(2)
+    print("launch per level", [(r["persistent"], r["order"]) for r in launch], flush=True)
+    g.mass()  # marks the start of the measured phase in the dispatch list
     g.step_coarse(steps)
     g.synchronize()
     tiles = {L: g.level_stats(L)["work_tiles"] for L in range(g.num_levels)}
@@ -82,30 +90,39 @@ def _db(path):
     return sqlite3.connect(path)
 
 
+def _measured_from(db):
+    """Dispatch id of the first reduction kernel (the start of the measured
+    phase), or 0 if there is none."""
+    rows = [d for n, d in db.execute("select name, dispatch_id from kernels") if "reduce_kernel" in n]
+    return min(rows) if rows else 0
+
+
 def trace_summary(results: str, out: str, command: str):
     db = _db(results)
-    rows = list(db.execute("select name, duration, grid_x, workgroup_x from kernels"))
+    first = _measured_from(db)
+    rows = list(db.execute("select name, duration, grid_x, workgroup_x, dispatch_id from kernels"))
     tiles = _finest_tiles()
     level_of_grid = {}
     for L, t in tiles.items():
         level_of_grid.setdefault(t, L)
     stats = {}
-    for name, dur, gx, wx in rows:
+    for name, dur, gx, wx, did in rows:
         key = name.rsplit("(", 1)[0]
         stats.setdefault(key, []).append(dur)
     per_level = {}
-    for name, dur, gx, wx in rows:
-        if "sweep_kernel" in name:
+    for name, dur, gx, wx, did in rows:
+        if "sweep_kernel" in name and did > first:
             L = level_of_grid.get(gx // max(wx, 1))
             per_level.setdefault((name.rsplit("(", 1)[0], L), []).append(dur)
     with open(out, "w") as fh:
         fh.write(f"# rocprofv3 --kernel-trace --stats summary\n# command: {command}\n")
-        fh.write("# durations in microseconds\n\n")
+        fh.write("# durations in microseconds; all dispatches of the run (autotuner candidates included)\n\n")
         fh.write(f"{'kernel':70s} {'calls':>6s} {'total_us':>12s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}\n")
         for k, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
             fh.write(f"{k[:70]:70s} {len(v):6d} {sum(v) / 1e3:12.1f} {sum(v) / len(v) / 1e3:10.2f} "
                      f"{min(v) / 1e3:10.2f} {max(v) / 1e3:10.2f}\n")
-        fh.write("\n# sweep launches by level (level from the grid size = work tiles of that level)\n")
+        fh.write(f"\n# measured phase (dispatches after the first reduce_kernel, id {first}): sweep launches by\n"
+                 "# level (level from the grid size = work tiles of that level; None = persistent grid)\n")
         for (k, L), v in sorted(per_level.items(), key=lambda kv: (kv[0][0], -1 if kv[0][1] is None else kv[0][1])):
             fh.write(f"{k[:60]:60s} level {L}: {len(v):5d} launches, avg {sum(v) / len(v) / 1e3:10.2f} us\n")
     print(open(out).read())
@@ -126,16 +143,15 @@ def traffic_summary(copy_fetch, copy_write, sweep_fetch, sweep_write, out, comma
     tiles = _finest_tiles()
     Lf = max(tiles)
     sys.path.insert(0, ROOT)
-    db = _db(sweep_fetch)
-    fin_f = [v for n, v, g, w in db.execute(
-        "select p.name, p.counter_value, k.grid_x, k.workgroup_x from pmc_events p join kernels k "
-        "on p.dispatch_id = k.dispatch_id where p.counter_name = 'FETCH_SIZE'") if "sweep_kernel" in n
-        and g // max(w, 1) == tiles[Lf]]
-    db = _db(sweep_write)
-    fin_w = [v for n, v, g, w in db.execute(
-        "select p.name, p.counter_value, k.grid_x, k.workgroup_x from pmc_events p join kernels k "
-        "on p.dispatch_id = k.dispatch_id where p.counter_name = 'WRITE_SIZE'") if "sweep_kernel" in n
-        and g // max(w, 1) == tiles[Lf]]
+    def finest(path, counter):
+        db = _db(path)
+        first = _measured_from(db)
+        return [v for n, v, g, w, d in db.execute(
+            "select p.name, p.counter_value, k.grid_x, k.workgroup_x, k.dispatch_id from pmc_events p join kernels k "
+            "on p.dispatch_id = k.dispatch_id where p.counter_name = ?", (counter,)) if "sweep_kernel" in n
+            and g // max(w, 1) == tiles[Lf] and d > first]
+    fin_f = finest(sweep_fetch, "FETCH_SIZE")
+    fin_w = finest(sweep_write, "WRITE_SIZE")
     if not fin_f or not fin_w:
         raise RuntimeError("finest-level sweep dispatches not found")
     fetch = sum(fin_f) / len(fin_f) * 1024.0 * fetch_scale
