@@ -186,9 +186,6 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   a.par = parent_cur;
   a.fine0 = fine0;
   a.fine1 = fine1;
-  a.plane = d.plane;
-  a.plane_par = L > 0 ? f->lv[L - 1].plane : 0;
-  a.plane_fine = L + 1 < nlev ? f->lv[L + 1].plane : 0;
   a.work = d.order == 1 && d.work_xcd ? d.work_xcd : d.work;
   a.nwork = d.nwork;
   a.substep = substep;
@@ -524,7 +521,7 @@ int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
     f->steps_since_state = 0;
     for (size_t L = 0; L < f->lv.size(); ++L) {
       const LevelDev& v = f->lv[L];
-      HIP_TRY(launch_init(f->storage, f->n, v.buf[0], v.plane, d_rho + off, d_u + 3 * off, v.ncells, f->stream));
+      HIP_TRY(launch_init(f->storage, f->n, v.buf[0], d_rho + off, d_u + 3 * off, v.ncells, f->stream));
       off += v.ncells;
     }
     HIP_TRY(hipStreamSynchronize(f->stream));
@@ -806,11 +803,9 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
     }
     const void** d_cur = nullptr;
     const void** d_post = nullptr;
-    uint64_t* d_planes = nullptr;
     int rc2;
     if ((rc2 = upload(scratch, &d_cur, cur))) return rc2;
     if ((rc2 = upload(scratch, &d_post, post))) return rc2;
-    if ((rc2 = upload(scratch, &d_planes, planes))) return rc2;
 
     std::vector<LevelDev> nlv;
     if ((rc2 = make_levels(n, sb, ntabs, nlv))) {
@@ -865,12 +860,10 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
       }
       RemapArgs ra;
       ra.dst = nlv[L].buf[0];
-      ra.dst_plane = nlv[L].plane;
       ra.blocks = d_rb;
       ra.ncells = int64_t(lv.size()) * int64_t(n3);
       ra.old_cur = d_cur;
       ra.old_post = d_post;
-      ra.old_plane = d_planes;
       ra.collide = have_post ? 1 : 0;
       const double p2 = std::ldexp(1.0, L);
       ra.omega64 = 2.0 * f->omega0 / (2.0 * p2 + (1.0 - p2) * f->omega0);
@@ -927,7 +920,7 @@ int lbm_get_moments(lbm_forest* f, double* rho, double* u) {
     double* d = nullptr;
     HIP_TRY(hipMalloc(&d, v.ncells * 4 * sizeof(double)));
     auto body = [&]() -> int {
-      HIP_TRY(launch_moments(f->storage, f->n, current_buffer(f, int(L)), v.plane, d, d + v.ncells, v.ncells, f->stream));
+      HIP_TRY(launch_moments(f->storage, f->n, current_buffer(f, int(L)), d, d + v.ncells, v.ncells, f->stream));
       HIP_TRY(hipMemcpyAsync(rho + off, d, v.ncells * sizeof(double), hipMemcpyDeviceToHost, f->stream));
       HIP_TRY(hipMemcpyAsync(u + 3 * off, d + v.ncells, v.ncells * 3 * sizeof(double), hipMemcpyDeviceToHost,
                              f->stream));
@@ -952,7 +945,7 @@ int lbm_get_pdfs(lbm_forest* f, double* h) {
     double* d = nullptr;
     HIP_TRY(hipMalloc(&d, v.ncells * 19 * sizeof(double)));
     auto body = [&]() -> int {
-      HIP_TRY(launch_get_pdfs(f->storage, f->n, current_buffer(f, int(L)), v.plane, d, v.ncells, f->stream));
+      HIP_TRY(launch_get_pdfs(f->storage, f->n, current_buffer(f, int(L)), d, v.ncells, f->stream));
       HIP_TRY(hipMemcpyAsync(h + 19 * off, d, v.ncells * 19 * sizeof(double), hipMemcpyDeviceToHost, f->stream));
       HIP_TRY(hipStreamSynchronize(f->stream));
       return LBM_OK;
@@ -976,7 +969,7 @@ int lbm_set_pdfs(lbm_forest* f, const double* h) {
     HIP_TRY(hipMalloc(&d, v.ncells * 19 * sizeof(double)));
     auto body = [&]() -> int {
       HIP_TRY(hipMemcpyAsync(d, h + 19 * off, v.ncells * 19 * sizeof(double), hipMemcpyHostToDevice, f->stream));
-      HIP_TRY(launch_set_pdfs(f->storage, f->n, current_buffer_mut(f, int(L)), v.plane, d, v.ncells, f->stream));
+      HIP_TRY(launch_set_pdfs(f->storage, f->n, current_buffer_mut(f, int(L)), d, v.ncells, f->stream));
       f->steps_since_state = 0;
       HIP_TRY(hipStreamSynchronize(f->stream));
       return LBM_OK;
@@ -997,7 +990,7 @@ int lbm_mass(lbm_forest* f, double* mass, double momentum[3]) {
   const size_t nl = f->lv.size();
   for (size_t L = 0; L < nl; ++L) {
     if (f->lv[L].ncells == 0) continue;
-    HIP_TRY(launch_reduce(f->storage, f->n, current_buffer(f, int(L)), f->lv[L].plane, f->lv[L].ncells,
+    HIP_TRY(launch_reduce(f->storage, f->n, current_buffer(f, int(L)), f->lv[L].ncells,
                           f->d_partials + L * kReduceGrid * 5, f->stream));
   }
   std::vector<double> part(nl * kReduceGrid * 5, 0.0);

@@ -53,7 +53,7 @@ constexpr int oW1 = 0, oB1 = oW1 + kHid * kFeat, oW2 = oB1 + kHid, oB2 = oW2 + k
 // Cells of the listed blocks (all blocks when `blocks` is null); outputs
 // are indexed like the level buffer (slot * n^3 + cell).
 template <typename S>
-__global__ void cell_stats_kernel(const S* buf, uint64_t plane, const int32_t* blocks, int64_t ncells, int n3,
+__global__ void cell_stats_kernel(const S* buf, const int32_t* blocks, int64_t ncells, int n3,
                                   double* drho, double* u, double* neq) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= ncells) return;
@@ -62,7 +62,7 @@ __global__ void cell_stats_kernel(const S* buf, uint64_t plane, const int32_t* b
   double s = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int a = 0; a < 19; ++a) {
-    h[a] = double(Form<S>::ld(buf + a * plane + idx));
+    h[a] = double(Form<S>::ld(buf + pdf_at_rt(a, uint64_t(idx), uint64_t(n3))));
     s += h[a];
     jx += ex(a) * h[a];
     jy += ey(a) * h[a];
@@ -154,7 +154,7 @@ __device__ void block_finish(double* acc, int n, double level_frac, double* fo, 
 // Features only, in one pass over the PDFs: no per-cell buffers and no
 // stencil (the |curl| accumulator stays zero and is not used).
 template <typename S>
-__global__ void __launch_bounds__(kStatThreads) block_features_kernel(const S* buf, uint64_t plane, int n,
+__global__ void __launch_bounds__(kStatThreads) block_features_kernel(const S* buf, int n,
                                                                       int nblocks, double level_frac,
                                                                       int64_t first, double* feat) {
   const int b = blockIdx.x;
@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(kStatThreads) block_features_kernel(const S* b
     double s = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int a = 0; a < 19; ++a) {
-      hv[a] = double(Form<S>::ld(buf + a * plane + idx));
+      hv[a] = double(Form<S>::ld(buf + pdf_at_rt(a, uint64_t(idx), uint64_t(n3))));
       s += hv[a];
       jx += ex(a) * hv[a];
       jy += ey(a) * hv[a];
@@ -494,22 +494,21 @@ int upload_features(lbm_mlp* m, Scratch& sc, const double* X, int64_t n, float**
 // `blocks` is null) with the two-pass cell / block kernels.
 int criterion_level(lbm_forest* f, int L, const void* buf, const int32_t* blocks, int nblocks, double* drho,
                     double* u, double* neq, int64_t first, double* dfeat, double* dcrit) {
-  const LevelDev& v = f->lv[L];
   const int n3 = f->n * f->n * f->n;
   const int64_t ncells = int64_t(nblocks) * n3;
   const unsigned g = grid_of(ncells, 256);
   switch (f->storage) {
     case LBM_F64:
       hipLaunchKernelGGL(cell_stats_kernel<double>, dim3(g), dim3(256), 0, f->stream, static_cast<const double*>(buf),
-                         v.plane, blocks, ncells, n3, drho, u, neq);
+                         blocks, ncells, n3, drho, u, neq);
       break;
     case LBM_F32:
       hipLaunchKernelGGL(cell_stats_kernel<float>, dim3(g), dim3(256), 0, f->stream, static_cast<const float*>(buf),
-                         v.plane, blocks, ncells, n3, drho, u, neq);
+                         blocks, ncells, n3, drho, u, neq);
       break;
     default:
       hipLaunchKernelGGL(cell_stats_kernel<__half>, dim3(g), dim3(256), 0, f->stream,
-                         static_cast<const __half*>(buf), v.plane, blocks, ncells, n3, drho, u, neq);
+                         static_cast<const __half*>(buf), blocks, ncells, n3, drho, u, neq);
   }
   TRY(hipGetLastError());
   const int nlev = int(f->lv.size());
@@ -531,15 +530,15 @@ int fused_features(lbm_forest* f, double* dfeat) {
     switch (f->storage) {
       case LBM_F64:
         hipLaunchKernelGGL(block_features_kernel<double>, dim3(v.nblocks), dim3(kStatThreads), 0, f->stream,
-                           static_cast<const double*>(buf), v.plane, f->n, v.nblocks, lf, first, dfeat);
+                           static_cast<const double*>(buf), f->n, v.nblocks, lf, first, dfeat);
         break;
       case LBM_F32:
         hipLaunchKernelGGL(block_features_kernel<float>, dim3(v.nblocks), dim3(kStatThreads), 0, f->stream,
-                           static_cast<const float*>(buf), v.plane, f->n, v.nblocks, lf, first, dfeat);
+                           static_cast<const float*>(buf), f->n, v.nblocks, lf, first, dfeat);
         break;
       default:
         hipLaunchKernelGGL(block_features_kernel<__half>, dim3(v.nblocks), dim3(kStatThreads), 0, f->stream,
-                           static_cast<const __half*>(buf), v.plane, f->n, v.nblocks, lf, first, dfeat);
+                           static_cast<const __half*>(buf), f->n, v.nblocks, lf, first, dfeat);
     }
     TRY(hipGetLastError());
     first += v.nblocks;
@@ -867,7 +866,7 @@ int lbm_refinement_flags(lbm_forest* f, lbm_mlp* m, double theta_omega, double t
     TRY(hipStreamSynchronize(f->stream));
     for (int64_t b = 0; b < nb; ++b) fallback += fb[b];
     if (fallback) {
-      // per-cell buffers are indexed like the level's PDF planes
+      // per-cell buffers are indexed by the canonical cell index
       TRY(sc.alloc(&drho, maxcells));
       TRY(sc.alloc(&du, 3 * maxcells));
       TRY(sc.alloc(&dneq, maxcells));

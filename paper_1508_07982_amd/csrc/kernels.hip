@@ -1,8 +1,7 @@
 // HIP helper kernels of the library (initial state, moments, raw PDF I/O,
 // FP64 reductions) and the storage dispatch of the sweep.  PDF buffers are
-// direction-major: element (a, slot, cell) at a * plane + slot * n^3 + cell;
-// interior cells of a level are addressed by their canonical index
-// slot * n^3 + cell.
+// block-major: element (a, slot, cell) at (19 slot + a) n^3 + cell; interior
+// cells of a level are addressed by their canonical index slot * n^3 + cell.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -23,7 +22,7 @@ using namespace dev;
 // ---- init / moments / raw I/O / reductions -------------------------------
 
 template <typename S, int N>
-__global__ void init_kernel(S* buf, uint64_t plane, const double* rho, const double* u, int64_t ncells) {
+__global__ void init_kernel(S* buf, const double* rho, const double* u, int64_t ncells) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= ncells) return;
   const double r = rho[idx], ux = u[3 * idx], uy = u[3 * idx + 1], uz = u[3 * idx + 2];
@@ -32,18 +31,18 @@ __global__ void init_kernel(S* buf, uint64_t plane, const double* rho, const dou
   for (int a = 0; a < 19; ++a) {
     const double eu = ex(a) * ux + ey(a) * uy + ez(a) * uz;
     const double h = wgt<double>(a) * ((r - 1.0) + 3.0 * eu + 4.5 * eu * eu - usq);
-    Form<S>::st(buf + a * plane + idx, typename Form<S>::C(h));
+    Form<S>::st(buf + pdf_at<N>(a, idx), typename Form<S>::C(h));
   }
 }
 
 template <typename S, int N>
-__global__ void moments_kernel(const S* buf, uint64_t plane, double* rho, double* u, int64_t ncells) {
+__global__ void moments_kernel(const S* buf, double* rho, double* u, int64_t ncells) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= ncells) return;
   double s = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int a = 0; a < 19; ++a) {
-    const double h = double(Form<S>::ld(buf + a * plane + idx));
+    const double h = double(Form<S>::ld(buf + pdf_at<N>(a, idx)));
     s += h;
     jx += ex(a) * h;
     jy += ey(a) * h;
@@ -56,20 +55,20 @@ __global__ void moments_kernel(const S* buf, uint64_t plane, double* rho, double
 }
 
 template <typename S, int N>
-__global__ void get_pdfs_kernel(const S* buf, uint64_t plane, double* h, int64_t ncells) {
+__global__ void get_pdfs_kernel(const S* buf, double* h, int64_t ncells) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= ncells) return;
 #pragma unroll
-  for (int a = 0; a < 19; ++a) h[idx * 19 + a] = double(Form<S>::ld(buf + a * plane + idx));
+  for (int a = 0; a < 19; ++a) h[idx * 19 + a] = double(Form<S>::ld(buf + pdf_at<N>(a, idx)));
 }
 
 template <typename S, int N>
-__global__ void set_pdfs_kernel(S* buf, uint64_t plane, const double* h, int64_t ncells) {
+__global__ void set_pdfs_kernel(S* buf, const double* h, int64_t ncells) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= ncells) return;
 #pragma unroll
   for (int a = 0; a < 19; ++a)
-    Form<S>::st(buf + a * plane + idx, typename Form<S>::C(h[idx * 19 + a]));
+    Form<S>::st(buf + pdf_at<N>(a, idx), typename Form<S>::C(h[idx * 19 + a]));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -83,14 +82,14 @@ constexpr int kReduceThreads = 256;
 // Deterministic FP64 partial sums: fixed grid, fixed per-thread stride,
 // wavefront butterfly, then a fixed-order sum over the 4 wavefronts.
 template <typename S, int N>
-__global__ void __launch_bounds__(kReduceThreads) reduce_kernel(const S* buf, uint64_t plane, int64_t ncells,
+__global__ void __launch_bounds__(kReduceThreads) reduce_kernel(const S* buf, int64_t ncells,
                                                                 double* out) {
   double acc[5] = {0, 0, 0, 0, 0};
   for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < ncells;
        idx += int64_t(gridDim.x) * blockDim.x) {
 #pragma unroll
     for (int a = 0; a < 19; ++a) {
-      const double h = double(Form<S>::ld(buf + a * plane + idx));
+      const double h = double(Form<S>::ld(buf + pdf_at<N>(a, idx)));
       acc[0] += h;
       acc[1] += ex(a) * h;
       acc[2] += ey(a) * h;
@@ -129,21 +128,18 @@ __global__ void remap_kernel(RemapArgs a) {
                                  : (rb.off[0] + (i >> rb.shift)) + N * ((rb.off[1] + (j >> rb.shift)) +
                                                                        N * (rb.off[2] + (k >> rb.shift)));
     const S* p = static_cast<const S*>(rb.mode == 0 ? a.old_cur[rb.src_level] : a.old_post[rb.src_level]);
-    const uint64_t plane = a.old_plane[rb.src_level];
 #pragma unroll
-    for (int d = 0; d < 19; ++d) h[d] = Form<S>::ld(p + d * plane + uint64_t(rb.slot[0]) * N3 + src);
+    for (int d = 0; d < 19; ++d) h[d] = Form<S>::ld(p + pdf_index<N>(d, uint32_t(rb.slot[0]), uint32_t(src)));
   } else {
     const int oct = (i >= H ? 1 : 0) | (j >= H ? 2 : 0) | (k >= H ? 4 : 0);
     const int cx = 2 * (i & (H - 1)), cy = 2 * (j & (H - 1)), cz = 2 * (k & (H - 1));
     const S* p = static_cast<const S*>(a.old_post[rb.src_level]);
-    const uint64_t plane = a.old_plane[rb.src_level];
-    const uint64_t base = uint64_t(rb.slot[oct]) * N3;
 #pragma unroll
     for (int d = 0; d < 19; ++d) {
       C s = C(0);
       for (int oz = 0; oz < 2; ++oz)
         for (int oy = 0; oy < 2; ++oy)
-          for (int ox = 0; ox < 2; ++ox) s += Form<S>::ld(p + d * plane + base + (cx + ox) + N * ((cy + oy) + N * (cz + oz)));
+          for (int ox = 0; ox < 2; ++ox) s += Form<S>::ld(p + pdf_index<N>(d, uint32_t(rb.slot[oct]), (cx + ox) + N * ((cy + oy) + N * (cz + oz))));
       h[d] = s * C(0.125);
     }
   }
@@ -168,7 +164,7 @@ __global__ void remap_kernel(RemapArgs a) {
   }
   S* out = static_cast<S*>(a.dst);
 #pragma unroll
-  for (int d = 0; d < 19; ++d) Form<S>::st(out + d * a.dst_plane + idx, h[d]);
+  for (int d = 0; d < 19; ++d) Form<S>::st(out + pdf_at<N>(d, idx), h[d]);
 }
 
 template <typename F>
@@ -211,50 +207,50 @@ hipError_t launch_sweep(int storage, int n, const SweepArgs& a, int grid, hipStr
   }
 }
 
-hipError_t launch_init(int storage, int n, void* buf, uint64_t plane, const double* rho, const double* u,
+hipError_t launch_init(int storage, int n, void* buf, const double* rho, const double* u,
                        int64_t ncells, hipStream_t stream) {
   if (ncells <= 0) return hipSuccess;
   return dispatch(storage, n, [&](auto s, auto nn) {
     using S = decltype(s);
     constexpr int N = decltype(nn)::value;
     hipLaunchKernelGGL((init_kernel<S, N>), dim3(grid_for(ncells, 256)), dim3(256), 0, stream, static_cast<S*>(buf),
-                       plane, rho, u, ncells);
+                       rho, u, ncells);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_moments(int storage, int n, const void* buf, uint64_t plane, double* rho, double* u,
+hipError_t launch_moments(int storage, int n, const void* buf, double* rho, double* u,
                           int64_t ncells, hipStream_t stream) {
   if (ncells <= 0) return hipSuccess;
   return dispatch(storage, n, [&](auto s, auto nn) {
     using S = decltype(s);
     constexpr int N = decltype(nn)::value;
     hipLaunchKernelGGL((moments_kernel<S, N>), dim3(grid_for(ncells, 256)), dim3(256), 0, stream,
-                       static_cast<const S*>(buf), plane, rho, u, ncells);
+                       static_cast<const S*>(buf), rho, u, ncells);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_get_pdfs(int storage, int n, const void* buf, uint64_t plane, double* h, int64_t ncells,
+hipError_t launch_get_pdfs(int storage, int n, const void* buf, double* h, int64_t ncells,
                            hipStream_t stream) {
   if (ncells <= 0) return hipSuccess;
   return dispatch(storage, n, [&](auto s, auto nn) {
     using S = decltype(s);
     constexpr int N = decltype(nn)::value;
     hipLaunchKernelGGL((get_pdfs_kernel<S, N>), dim3(grid_for(ncells, 256)), dim3(256), 0, stream,
-                       static_cast<const S*>(buf), plane, h, ncells);
+                       static_cast<const S*>(buf), h, ncells);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_set_pdfs(int storage, int n, void* buf, uint64_t plane, const double* h, int64_t ncells,
+hipError_t launch_set_pdfs(int storage, int n, void* buf, const double* h, int64_t ncells,
                            hipStream_t stream) {
   if (ncells <= 0) return hipSuccess;
   return dispatch(storage, n, [&](auto s, auto nn) {
     using S = decltype(s);
     constexpr int N = decltype(nn)::value;
     hipLaunchKernelGGL((set_pdfs_kernel<S, N>), dim3(grid_for(ncells, 256)), dim3(256), 0, stream,
-                       static_cast<S*>(buf), plane, h, ncells);
+                       static_cast<S*>(buf), h, ncells);
     return hipGetLastError();
   });
 }
@@ -269,13 +265,13 @@ hipError_t launch_remap(int storage, int n, const RemapArgs& a, hipStream_t stre
   });
 }
 
-hipError_t launch_reduce(int storage, int n, const void* buf, uint64_t plane, int64_t ncells, double* out,
+hipError_t launch_reduce(int storage, int n, const void* buf, int64_t ncells, double* out,
                          hipStream_t stream) {
   return dispatch(storage, n, [&](auto s, auto nn) {
     using S = decltype(s);
     constexpr int N = decltype(nn)::value;
     hipLaunchKernelGGL((reduce_kernel<S, N>), dim3(kReduceGrid), dim3(kReduceThreads), 0, stream,
-                       static_cast<const S*>(buf), plane, ncells, out);
+                       static_cast<const S*>(buf), ncells, out);
     return hipGetLastError();
   });
 }

@@ -8,7 +8,7 @@
 namespace lbm {
 
 // Arguments of one level substep of the fused sweep.  PDF buffers are
-// direction-major: element (a, slot, cell) sits at a * plane + slot * n^3 + cell.
+// block-major: element (a, slot, cell) sits at (19 slot + a) n^3 + cell.
 // Levels L >= 1 keep three buffers: the state at the start of the parent
 // step (t), after the first substep (t + 1/2) and after the second (t + 1).
 struct SweepArgs {
@@ -18,9 +18,6 @@ struct SweepArgs {
   const void* par;            // level-(L-1) post-collision state (explosion source)
   const void* fine0;          // level-(L+1) state at the start of its last parent step
   const void* fine1;          // level-(L+1) state after the first of its two substeps
-  uint64_t plane;             // elements per direction of level L   (blocks * n^3)
-  uint64_t plane_par;         // same for level L-1
-  uint64_t plane_fine;        // same for level L+1
   const int32_t* work;        // work tiles: slot * tiles_per_block + tile
   int32_t nwork;
   int32_t substep;            // 1 or 2
@@ -42,27 +39,27 @@ int sweep_tile_cells(int storage, int n);
 // storage: 0 = f64, 1 = f32, 2 = f16
 hipError_t launch_sweep(int storage, int n, const SweepArgs& a, int grid, hipStream_t stream);
 
-// The helpers below address the interior cells [0, ncells) of one level,
-// whose buffer has `plane` elements per direction.
+// The helpers below address the interior cells [0, ncells) of one level
+// (block-major buffer: element (a, slot, cell) at (19 slot + a) n^3 + cell).
 
 // h = f^eq(rho, u) - w.
-hipError_t launch_init(int storage, int n, void* buf, uint64_t plane, const double* rho, const double* u,
+hipError_t launch_init(int storage, int n, void* buf, const double* rho, const double* u,
                        int64_t ncells, hipStream_t stream);
 
 // rho = 1 + sum h, u = sum e h.
-hipError_t launch_moments(int storage, int n, const void* buf, uint64_t plane, double* rho, double* u,
+hipError_t launch_moments(int storage, int n, const void* buf, double* rho, double* u,
                           int64_t ncells, hipStream_t stream);
 
 // Raw shifted PDFs, FP64 [cell][19].
-hipError_t launch_get_pdfs(int storage, int n, const void* buf, uint64_t plane, double* h, int64_t ncells,
+hipError_t launch_get_pdfs(int storage, int n, const void* buf, double* h, int64_t ncells,
                            hipStream_t stream);
-hipError_t launch_set_pdfs(int storage, int n, void* buf, uint64_t plane, const double* h, int64_t ncells,
+hipError_t launch_set_pdfs(int storage, int n, void* buf, const double* h, int64_t ncells,
                            hipStream_t stream);
 
 // FP64 partial sums (sum h, sum e_x h, sum e_y h, sum e_z h, nonfinite count);
 // kReduceGrid workgroups write out[kReduceGrid][5].
 constexpr int kReduceGrid = 1024;
-hipError_t launch_reduce(int storage, int n, const void* buf, uint64_t plane, int64_t ncells, double* out,
+hipError_t launch_reduce(int storage, int n, const void* buf, int64_t ncells, double* out,
                          hipStream_t stream);
 
 // Regrid remap of one new level.  Each new block takes its PDFs from the old
@@ -80,13 +77,11 @@ struct RemapBlock {
 };
 
 struct RemapArgs {
-  void* dst;                  // new level buffer (state written as slot-major canonical cells)
-  uint64_t dst_plane;
+  void* dst;                  // new level buffer
   const RemapBlock* blocks;   // one per new block
   int64_t ncells;             // new blocks * n^3
   const void* const* old_cur;   // per old level: current (post-collision) state
   const void* const* old_post;  // per old level: post-streaming values of changed blocks
-  const uint64_t* old_plane;    // per old level
   int32_t collide;
   float omega;
   double omega64;

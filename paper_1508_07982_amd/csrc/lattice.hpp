@@ -27,6 +27,28 @@ __host__ __device__ constexpr C wgt(int a) {
   return a == 0 ? C(1) / C(3) : (a <= 6 ? C(1) / C(18) : C(1) / C(36));
 }
 
+// ---- PDF layout --------------------------------------------------------------
+// A level buffer is block-major: block `slot` holds its 19 direction planes
+// of n^3 cells one after the other, element (a, slot, cell) at
+// (19 slot + a) n^3 + cell.  The 19 rows a tile reads then lie inside one
+// block's 19 n^3 elements, which measured faster than direction planes
+// spanning the whole level.  Interior cells keep their canonical index
+// idx = slot * n^3 + cell.
+constexpr int kQ = 19;
+template <int N>
+__host__ __device__ constexpr uint64_t pdf_index(int a, uint64_t slot, uint32_t cell) {
+  return (slot * kQ + uint64_t(a)) * uint64_t(N * N * N) + cell;
+}
+template <int N>
+__host__ __device__ constexpr uint64_t pdf_at(int a, uint64_t idx) {
+  constexpr uint64_t N3 = uint64_t(N) * N * N;
+  return (idx / N3 * kQ + uint64_t(a)) * N3 + idx % N3;
+}
+// the same for a block size known only at run time
+__host__ __device__ inline uint64_t pdf_at_rt(int a, uint64_t idx, uint64_t n3) {
+  return (idx / n3 * kQ + uint64_t(a)) * n3 + idx % n3;
+}
+
 // ---- storage forms --------------------------------------------------------
 template <typename S>
 struct Form;

@@ -17,7 +17,7 @@ inline size_t storage_bytes(int storage) { return storage == LBM_F64 ? 8 : (stor
 
 struct LevelDev {
   int64_t ncells = 0;  // interior cells
-  uint64_t plane = 0;  // elements per direction plane: blocks * n^3
+  uint64_t plane = 0;  // cells per direction: blocks * n^3 (a buffer holds 19 plane elements)
   int nblocks = 0, nwork = 0, tiles_per_block = 0;
   int nbuf = 0;
   void* buf[3] = {nullptr, nullptr, nullptr};

@@ -27,9 +27,9 @@
 // the shifted form: drho = sum h, u = sum e h, h_eq = w (drho + 3 e.u +
 // 4.5 (e.u)^2 - 1.5 u^2), h <- h + omega (h_eq - h).
 //
-// Memory layout per level: [direction][slot][z][y][x], one slot per block,
-// so a 64-lane wavefront reads 64 consecutive cells of one direction, and a
-// direction plane is addressed by a uniform base plus a 32-bit cell offset.
+// Memory layout per level: [slot][direction][z][y][x] (block-major, one
+// slot per block), so a 64-lane wavefront reads 64 consecutive cells of one
+// direction and the 19 rows of a tile lie inside one block's storage.
 #pragma once
 
 #include "forest.hpp"
@@ -55,11 +55,11 @@ __device__ __forceinline__ int side(int c) {
 // parent's post-collision value (homogeneous explosion, eq. ctof).
 template <typename S, int N, int A>
 __device__ __forceinline__ typename Form<S>::C parent_value(const SweepArgs& a, int code, int lx, int ly, int lz) {
-  constexpr int N3 = Geo<S, N>::N3, H = Geo<S, N>::H;
+  constexpr int H = Geo<S, N>::H;
   const int pp = kNbrCoarse0 - code;
   const int oc = pp & 7;
   const int px = (oc & 1 ? H : 0) + (lx >> 1), py = (oc & 2 ? H : 0) + (ly >> 1), pz = (oc & 4 ? H : 0) + (lz >> 1);
-  const S* p = static_cast<const S*>(a.par) + A * a.plane_par + uint32_t(pp >> 3) * N3;
+  const S* p = static_cast<const S*>(a.par) + pdf_index<N>(A, uint32_t(pp >> 3), 0);
   return Form<S>::ld(p + px + N * (py + N * pz));
 }
 
@@ -82,7 +82,7 @@ template <typename S, int N, int A>
 __device__ __forceinline__ typename Form<S>::C special_value(const SweepArgs& a, const SlotCache& sc, int slot, int i,
                                                              int j, int k, bool co, typename Form<S>::C regular) {
   using C = typename Form<S>::C;
-  constexpr int N3 = Geo<S, N>::N3, H = Geo<S, N>::H;
+  constexpr int H = Geo<S, N>::H;
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
   if (co) {
     const int oct = (i >= H ? 1 : 0) | (j >= H ? 2 : 0) | (k >= H ? 4 : 0);
@@ -92,8 +92,8 @@ __device__ __forceinline__ typename Form<S>::C special_value(const SweepArgs& a,
       return C(0);
     }
     const int32_t* fn = a.fine_nbr + (row * 8 + oct) * 27;
-    const S* f1 = static_cast<const S*>(a.fine1) + A * a.plane_fine;
-    const S* f0 = static_cast<const S*>(a.fine0) + A * a.plane_fine;
+    const S* f1 = static_cast<const S*>(a.fine1);
+    const S* f0 = static_cast<const S*>(a.fine0);
     const int cx = 2 * (i & (H - 1)), cy = 2 * (j & (H - 1)), cz = 2 * (k & (H - 1));
     C s = C(0);
 #pragma unroll
@@ -105,12 +105,12 @@ __device__ __forceinline__ typename Form<S>::C special_value(const SweepArgs& a,
           const int yx = cx + ox - EX, yy = cy + oy - EY, yz = cz + oz - EZ;
           const int fy = fn[13 + side<N>(yx) + 3 * side<N>(yy) + 9 * side<N>(yz)];
           if (fy >= 0) {
-            s += Form<S>::ld(f1 + uint32_t(fy) * N3 + (yx & (N - 1)) + N * ((yy & (N - 1)) + N * (yz & (N - 1))));
+            s += Form<S>::ld(f1 + pdf_index<N>(A, uint32_t(fy), 0) + (yx & (N - 1)) + N * ((yy & (N - 1)) + N * (yz & (N - 1))));
           } else {
             const int zx = yx - EX, zy = yy - EY, zz = yz - EZ;
             const int fz = fn[13 + side<N>(zx) + 3 * side<N>(zy) + 9 * side<N>(zz)];
             if (fz >= 0)
-              s += Form<S>::ld(f0 + uint32_t(fz) * N3 + (zx & (N - 1)) + N * ((zy & (N - 1)) + N * (zz & (N - 1))));
+              s += Form<S>::ld(f0 + pdf_index<N>(A, uint32_t(fz), 0) + (zx & (N - 1)) + N * ((zy & (N - 1)) + N * (zz & (N - 1))));
             else
               s += regular;
           }
@@ -127,7 +127,7 @@ __device__ __forceinline__ typename Form<S>::C special_value(const SweepArgs& a,
   const int zx = sx - EX, zy = sy - EY, zz = sz - EZ;
   const int cz = sc.nbr[13 + side<N>(zx) + 3 * side<N>(zy) + 9 * side<N>(zz)];
   if (cz >= 0) {
-    const S* p = static_cast<const S*>(a.prev) + A * a.plane + uint32_t(cz) * N3;
+    const S* p = static_cast<const S*>(a.prev) + pdf_index<N>(A, uint32_t(cz), 0);
     return Form<S>::ld(p + (zx & (N - 1)) + N * ((zy & (N - 1)) + N * (zz & (N - 1))));
   }
   if (cz > kNbrCoarse0) {
@@ -159,7 +159,7 @@ template <typename S, int N, int A, bool SIMPLE>
 __device__ __forceinline__ void issue_dir(const SweepArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
                                           typename Form<S>::C (*h)[Geo<S, N>::W], typename Form<S>::C* edge,
                                           uint32_t& odd) {
-  constexpr int W = Geo<S, N>::W, N3 = Geo<S, N>::N3;
+  constexpr int W = Geo<S, N>::W;
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
   const int sy = j - EY, sz = k - EZ;
   const int oy = EY == 0 ? 0 : side<N>(sy);
@@ -168,8 +168,8 @@ __device__ __forceinline__ void issue_dir(const SweepArgs& a, const SlotCache& s
   const int dmain = 13 + 3 * oy + 9 * oz;
   const int nbm = sc.nbr[dmain];
   if (!SIMPLE) odd |= uint32_t(nbm < 0);
-  const S* __restrict__ base = static_cast<const S*>(a.cur) + A * a.plane;
-  const uint32_t bm = uint32_t(SIMPLE || nbm >= 0 ? nbm : slot) * N3 + row + uint32_t(i0);
+  const S* __restrict__ base = static_cast<const S*>(a.cur);
+  const uint64_t bm = pdf_index<N>(A, uint32_t(SIMPLE || nbm >= 0 ? nbm : slot), row + uint32_t(i0));
   Vec<S>::load(base + bm, h[A]);
   if constexpr (EX != 0) {
     const bool at_end = EX == 1 ? i0 == 0 : i0 == N - W;
@@ -178,7 +178,7 @@ __device__ __forceinline__ void issue_dir(const SweepArgs& a, const SlotCache& s
     // the lane at the end of the row reads the neighbour row's end element,
     // the others the end element of their own source row (in bounds, unused)
     const int eb = at_end ? (SIMPLE || nbx >= 0 ? nbx : slot) : (SIMPLE || nbm >= 0 ? nbm : slot);
-    edge[xdir_index(A)] = Form<S>::ld(base + uint32_t(eb) * N3 + row + uint32_t(EX == 1 ? N - 1 : 0));
+    edge[xdir_index(A)] = Form<S>::ld(base + pdf_index<N>(A, uint32_t(eb), row + uint32_t(EX == 1 ? N - 1 : 0)));
   }
 }
 
@@ -306,9 +306,9 @@ __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache&
 #pragma unroll
     for (int c = 0; c < W; ++c) collide<C, W>(h, c, om);
   }
-  S* __restrict__ nxt = static_cast<S*>(a.nxt) + uint32_t(slot) * N3 + uint32_t(cell0);
+  S* __restrict__ nxt = static_cast<S*>(a.nxt) + pdf_index<N>(0, uint32_t(slot), uint32_t(cell0));
 #pragma unroll
-  for (int d = 0; d < 19; ++d) Vec<S>::store(nxt + d * a.plane, h[d]);
+  for (int d = 0; d < 19; ++d) Vec<S>::store(nxt + d * N3, h[d]);
 }
 
 // ---- packed FP16 path: 8 cells per lane as 4 registers of half pairs ------
@@ -335,7 +335,6 @@ __device__ __forceinline__ uint32_t dpp_move_u32(uint32_t v) {
 template <int N, int A, bool SIMPLE>
 __device__ __forceinline__ void issue_dir_h8(const SweepArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
                                              uint32_t (*q)[4], uint32_t* edge, uint32_t& odd) {
-  constexpr int N3 = N * N * N;
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
   const int sy = j - EY, sz = k - EZ;
   const int oy = EY == 0 ? 0 : side<N>(sy);
@@ -344,16 +343,16 @@ __device__ __forceinline__ void issue_dir_h8(const SweepArgs& a, const SlotCache
   const int dmain = 13 + 3 * oy + 9 * oz;
   const int nbm = sc.nbr[dmain];
   if (!SIMPLE) odd |= uint32_t(nbm < 0);
-  const uint16_t* __restrict__ base = static_cast<const uint16_t*>(a.cur) + A * a.plane;
+  const uint16_t* __restrict__ base = static_cast<const uint16_t*>(a.cur);
   const int bms = SIMPLE || nbm >= 0 ? nbm : slot;
-  const uint4 v = *reinterpret_cast<const uint4*>(base + uint32_t(bms) * N3 + row + uint32_t(i0));
+  const uint4 v = *reinterpret_cast<const uint4*>(base + pdf_index<N>(A, uint32_t(bms), row + uint32_t(i0)));
   q[A][0] = v.x, q[A][1] = v.y, q[A][2] = v.z, q[A][3] = v.w;
   if constexpr (EX != 0) {
     const bool at_end = EX == 1 ? i0 == 0 : i0 == N - 8;
     const int nbx = sc.nbr[dmain - EX];
     if (!SIMPLE) odd |= uint32_t(at_end && nbx < 0);
     const int eb = at_end ? (SIMPLE || nbx >= 0 ? nbx : slot) : bms;
-    edge[xdir_index(A)] = base[uint32_t(eb) * N3 + row + uint32_t(EX == 1 ? N - 1 : 0)];
+    edge[xdir_index(A)] = base[pdf_index<N>(A, uint32_t(eb), row + uint32_t(EX == 1 ? N - 1 : 0))];
   }
 }
 
@@ -432,11 +431,11 @@ __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCac
       for (int d = 0; d < 19; ++d) q[d][p] = pack_pair(h[d][0], h[d][1]);
     }
   }
-  uint16_t* __restrict__ nxt = static_cast<uint16_t*>(a.nxt) + uint32_t(slot) * N3 + uint32_t(cell0);
+  uint16_t* __restrict__ nxt = static_cast<uint16_t*>(a.nxt) + pdf_index<N>(0, uint32_t(slot), uint32_t(cell0));
 #pragma unroll
   for (int d = 0; d < 19; ++d) {
     const u32x4 t = {q[d][0], q[d][1], q[d][2], q[d][3]};
-    __builtin_nontemporal_store(t, reinterpret_cast<u32x4*>(nxt + d * a.plane));
+    __builtin_nontemporal_store(t, reinterpret_cast<u32x4*>(nxt + d * N3));
   }
 }
 
