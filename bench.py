@@ -88,6 +88,29 @@ def launch_table(res):
     return {f"L{r['level']}": [r["persistent"], r["order"]] for r in res}
 
 
+def batching_form(torch, lbm, W, stream):
+    """Time per coarse step on the 8.57 M-cell slab + sphere grid of 16^3
+    blocks (uneven block counts per level): the whole step as one graph with
+    autotuned launch shapes, direct launches, and one launch per block."""
+    wb = W.config_slab_sphere(16, 5)
+    out = {"workload": wb.name, "description": wb.description}
+    for label, schedule, tune in (("graph_autotuned", "graph", True), ("direct", "direct", False),
+                                  ("per_block", "per_block", False)):
+        g = make_forest(lbm, W, wb, "f32", stream.cuda_stream)
+        if label == "graph_autotuned":
+            out["cells"] = g.num_cells()
+            out["blocks_per_level"] = [g.num_blocks(L) for L in range(g.num_levels)]
+            out["launch"] = launch_table(g.autotune(2))
+        g.set_schedule(schedule)
+        g.step_coarse(2)
+        ms = timed_steps(torch, g, stream, 20 if label != "per_block" else 3)
+        out[f"{label}_ms_per_step"] = round(ms, 4)
+        out[f"{label}_MLUPS"] = round(g.updates_per_coarse_step() / (ms * 1e-3) / 1e6, 1)
+        g.close()
+        del g
+    return out
+
+
 def cpu_baseline(W, budget_s: float = 12.0):
     """The FP64 oracle on the same sphere-shell geometry with 8^3-cell
     blocks (1/64 of the cells), timed over as many coarse steps as fit in
@@ -175,6 +198,7 @@ def main():
                               "launch": launch_table(launch16), "mass_drift": abs(M16b - M16a) / M16a}
         g16.close()
         del g16
+        forms["batching_slab_sphere"] = batching_form(torch, lbm, W, stream)
         gp = make_forest(lbm, W, w, "f32", stream.cuda_stream)
         gp.set_schedule("per_block")
         gp.step_coarse(1)
