@@ -39,9 +39,12 @@
 namespace lbm {
 namespace dev {
 
-// Per-workgroup copy of the slot's neighbour table.
+// Per-workgroup copy of the slot's neighbour table and, for a slot with
+// finer neighbours, of the neighbour tables of its 8 virtual level-(L+1)
+// blocks (octant-major).
 struct SlotCache {
   int32_t nbr[27];
+  int32_t fine_nbr[8 * 27];
 };
 
 // Neighbour offset (-1, 0, +1) of a local coordinate after a shift.
@@ -50,91 +53,92 @@ __device__ __forceinline__ int side(int c) {
   return c < 0 ? -1 : (c >= N ? 1 : 0);
 }
 
-// Value at level-L cell (lx, ly, lz) of the virtual block whose neighbour
+// Address of level-L cell (lx, ly, lz) of the virtual block whose neighbour
 // table entry is `code` (< kNbrFine, i.e. inside a level-(L-1) leaf): the
 // parent's post-collision value (homogeneous explosion, eq. ctof).
 template <typename S, int N, int A>
-__device__ __forceinline__ typename Form<S>::C parent_value(const SweepArgs& a, int code, int lx, int ly, int lz) {
+__device__ __forceinline__ const S* parent_ptr(const SweepArgs& a, int code, int lx, int ly, int lz) {
   constexpr int H = Geo<S, N>::H;
   const int pp = kNbrCoarse0 - code;
   const int oc = pp & 7;
   const int px = (oc & 1 ? H : 0) + (lx >> 1), py = (oc & 2 ? H : 0) + (ly >> 1), pz = (oc & 4 ? H : 0) + (lz >> 1);
-  const S* p = static_cast<const S*>(a.par) + pdf_index<N>(A, uint32_t(pp >> 3), 0);
-  return Form<S>::ld(p + px + N * (py + N * pz));
+  return static_cast<const S*>(a.par) + pdf_index<N>(A, uint32_t(pp >> 3), uint32_t(px + N * (py + N * pz)));
 }
 
-// Value of a special source of cell (i, j, k) of slot `slot`, direction A.
-//
-// Coalescence (eq. ftoc, co == true): the mean over the 8 children c of the
-// cell of the value the child holds after the finer level's two substeps,
-// i.e. what the second fine stream pulled into c from c - e_A:
-//   c - e_A in a level-(L+1) block  -> that cell's state after substep 1;
-//   otherwise c - e_A is a halo cell, whose first-substep value came from
-//   c - 2 e_A: the fine state at t if that is a level-(L+1) cell, else the
-//   exploded coarse value, which is this cell's ordinary source `regular`.
+// Special sources of cell (i, j, k), direction A.
 //
 // Coarse source (the cell x - e_A lies in a level-(L-1) leaf):
 //   substep 1: the exploded parent value of x - e_A;
 //   substep 2: x - e_A is a halo cell whose first-substep value was pulled
 //   from x - 2 e_A: the level's own state at t there, or the exploded parent
 //   value if x - 2 e_A is also in the coarse region.
+// coarse_source returns its address (an inconsistent table sets an error
+// bit and yields an in-bounds dummy address), so that the loads of all
+// cells of a lane can be issued together.
 template <typename S, int N, int A>
-__device__ __forceinline__ typename Form<S>::C special_value(const SweepArgs& a, const SlotCache& sc, int slot, int i,
-                                                             int j, int k, bool co, typename Form<S>::C regular) {
-  using C = typename Form<S>::C;
-  constexpr int H = Geo<S, N>::H;
+__device__ __forceinline__ const S* coarse_source(const SweepArgs& a, const SlotCache& sc, int i, int j, int k) {
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
-  if (co) {
-    const int oct = (i >= H ? 1 : 0) | (j >= H ? 2 : 0) | (k >= H ? 4 : 0);
-    const int row = a.fine_index[slot];
-    if (row < 0) {
-      atomicOr(a.err, kErrNoChild);
-      return C(0);
-    }
-    const int32_t* fn = a.fine_nbr + (row * 8 + oct) * 27;
-    const S* f1 = static_cast<const S*>(a.fine1);
-    const S* f0 = static_cast<const S*>(a.fine0);
-    const int cx = 2 * (i & (H - 1)), cy = 2 * (j & (H - 1)), cz = 2 * (k & (H - 1));
-    C s = C(0);
-#pragma unroll
-    for (int oz = 0; oz < 2; ++oz)
-#pragma unroll
-      for (int oy = 0; oy < 2; ++oy)
-#pragma unroll
-        for (int ox = 0; ox < 2; ++ox) {
-          const int yx = cx + ox - EX, yy = cy + oy - EY, yz = cz + oz - EZ;
-          const int fy = fn[13 + side<N>(yx) + 3 * side<N>(yy) + 9 * side<N>(yz)];
-          if (fy >= 0) {
-            s += Form<S>::ld(f1 + pdf_index<N>(A, uint32_t(fy), 0) + (yx & (N - 1)) + N * ((yy & (N - 1)) + N * (yz & (N - 1))));
-          } else {
-            const int zx = yx - EX, zy = yy - EY, zz = yz - EZ;
-            const int fz = fn[13 + side<N>(zx) + 3 * side<N>(zy) + 9 * side<N>(zz)];
-            if (fz >= 0)
-              s += Form<S>::ld(f0 + pdf_index<N>(A, uint32_t(fz), 0) + (zx & (N - 1)) + N * ((zy & (N - 1)) + N * (zz & (N - 1))));
-            else
-              s += regular;
-          }
-        }
-    return s * C(0.125);
-  }
+  const S* dummy = static_cast<const S*>(a.cur);
   const int sx = i - EX, sy = j - EY, sz = k - EZ;
   const int code = sc.nbr[13 + side<N>(sx) + 3 * side<N>(sy) + 9 * side<N>(sz)];
   if (code > kNbrCoarse0) {  // not a coarse region: never expected here
     atomicOr(a.err, kErrNoSource);
-    return C(0);
+    return dummy;
   }
-  if (a.substep == 1) return parent_value<S, N, A>(a, code, sx & (N - 1), sy & (N - 1), sz & (N - 1));
+  if (a.substep == 1) return parent_ptr<S, N, A>(a, code, sx & (N - 1), sy & (N - 1), sz & (N - 1));
   const int zx = sx - EX, zy = sy - EY, zz = sz - EZ;
   const int cz = sc.nbr[13 + side<N>(zx) + 3 * side<N>(zy) + 9 * side<N>(zz)];
-  if (cz >= 0) {
-    const S* p = static_cast<const S*>(a.prev) + pdf_index<N>(A, uint32_t(cz), 0);
-    return Form<S>::ld(p + (zx & (N - 1)) + N * ((zy & (N - 1)) + N * (zz & (N - 1))));
-  }
+  if (cz >= 0)
+    return static_cast<const S*>(a.prev) +
+           pdf_index<N>(A, uint32_t(cz), uint32_t((zx & (N - 1)) + N * ((zy & (N - 1)) + N * (zz & (N - 1)))));
   if (cz > kNbrCoarse0) {
     atomicOr(a.err, kErrNoSource);
-    return C(0);
+    return dummy;
   }
-  return parent_value<S, N, A>(a, cz, zx & (N - 1), zy & (N - 1), zz & (N - 1));
+  return parent_ptr<S, N, A>(a, cz, zx & (N - 1), zy & (N - 1), zz & (N - 1));
+}
+
+// Coalescence (eq. ftoc): the mean over the 8 children c of the cell of the
+// value the child holds after the finer level's two substeps, i.e. what the
+// second fine stream pulled into c from c - e_A:
+//   c - e_A in a level-(L+1) block  -> that cell's state after substep 1;
+//   otherwise c - e_A is a halo cell, whose first-substep value came from
+//   c - 2 e_A: the fine state at t if that is a level-(L+1) cell, else the
+//   exploded coarse value, which is this cell's ordinary source `regular`.
+// The 8 loads carry no branch (a child without a fine source loads a dummy
+// address and takes `regular`), so they are in flight together.
+template <typename S, int N, int A>
+__device__ __forceinline__ typename Form<S>::C coalesced_value(const SweepArgs& a, const SlotCache& sc, int i, int j,
+                                                               int k, typename Form<S>::C regular) {
+  using C = typename Form<S>::C;
+  constexpr int H = Geo<S, N>::H;
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  const int oct = (i >= H ? 1 : 0) | (j >= H ? 2 : 0) | (k >= H ? 4 : 0);
+  const int32_t* fn = sc.fine_nbr + oct * 27;
+  const S* f1 = static_cast<const S*>(a.fine1);
+  const S* f0 = static_cast<const S*>(a.fine0);
+  const S* dummy = static_cast<const S*>(a.cur);
+  const int cx = 2 * (i & (H - 1)), cy = 2 * (j & (H - 1)), cz = 2 * (k & (H - 1));
+  C v[8];
+  bool fine[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int yx = cx + (q & 1) - EX, yy = cy + ((q >> 1) & 1) - EY, yz = cz + (q >> 2) - EZ;
+    const int fy = fn[13 + side<N>(yx) + 3 * side<N>(yy) + 9 * side<N>(yz)];
+    const int zx = yx - EX, zy = yy - EY, zz = yz - EZ;
+    const int fz = fn[13 + side<N>(zx) + 3 * side<N>(zy) + 9 * side<N>(zz)];
+    const S* p = fy >= 0 ? f1 + pdf_index<N>(A, uint32_t(fy), uint32_t((yx & (N - 1)) + N * ((yy & (N - 1)) +
+                                                                                          N * (yz & (N - 1)))))
+               : fz >= 0 ? f0 + pdf_index<N>(A, uint32_t(fz), uint32_t((zx & (N - 1)) + N * ((zy & (N - 1)) +
+                                                                                          N * (zz & (N - 1)))))
+                         : dummy;
+    fine[q] = fy >= 0 || fz >= 0;
+    v[q] = Form<S>::ld(p);
+  }
+  C s = C(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s += fine[q] ? v[q] : regular;
+  return s * C(0.125);
 }
 
 // Index of direction A among the 10 directions with a nonzero x component.
@@ -254,42 +258,67 @@ __device__ __forceinline__ uint32_t special_cells(const SlotCache& sc, uint32_t 
   return spec;
 }
 
+// Special sources of direction A for the W cells of a lane: the coarse
+// sources' loads are issued together, then the coalesced cells one by one.
 template <typename S, int N, int A = 0>
-__device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl, int i0, int j,
-                                       int k, typename Form<S>::C (*h)[Geo<S, N>::W]) {
+__device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, uint32_t fl, int i0, int j, int k,
+                                       typename Form<S>::C (*h)[Geo<S, N>::W]) {
+  using C = typename Form<S>::C;
   constexpr int W = Geo<S, N>::W;
   uint32_t co;
   const uint32_t spec = special_cells<N, W, A>(sc, fl, i0, j, k, co);
-  if (spec) {
+  const uint32_t cs = spec & ~co;
+  if (cs) {
+    C v[W];
 #pragma unroll
     for (int c = 0; c < W; ++c)
-      if ((spec >> c) & 1u) h[A][c] = special_value<S, N, A>(a, sc, slot, i0 + c, j, k, (co >> c) & 1u, h[A][c]);
+      v[c] = Form<S>::ld((cs >> c) & 1u ? coarse_source<S, N, A>(a, sc, i0 + c, j, k) : static_cast<const S*>(a.cur));
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+      if ((cs >> c) & 1u) h[A][c] = v[c];
   }
-  if constexpr (A + 1 < 19) fixups<S, N, A + 1>(a, sc, slot, fl, i0, j, k, h);
+  if (co) {
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+      if ((co >> c) & 1u) h[A][c] = coalesced_value<S, N, A>(a, sc, i0 + c, j, k, h[A][c]);
+  }
+  if constexpr (A + 1 < 19) fixups<S, N, A + 1>(a, sc, fl, i0, j, k, h);
 }
 
-template <typename C, int W, int A = 0>
-__device__ __forceinline__ void relax(C (*h)[W], int c, C drho, C ux, C uy, C uz, C usq, C om) {
-  constexpr C w = wgt<C>(A);
-  const C eu = C(ex(A)) * ux + C(ey(A)) * uy + C(ez(A)) * uz;
-  const C heq = w * (drho + C(3) * eu + C(4.5) * eu * eu - usq);
-  h[A][c] = h[A][c] + om * (heq - h[A][c]);
-  if constexpr (A + 1 < 19) relax<C, W, A + 1>(h, c, drho, ux, uy, uz, usq, om);
+// Relaxation of the opposite pair (A, A + 1), e_{A+1} = -e_A: with
+// t = e_A . u the two equilibria share the even part w (drho - 1.5 u^2 +
+// 4.5 t^2) and differ in the sign of the odd part 3 w t, and
+// h + omega (h_eq - h) = (1 - omega) h + omega h_eq.
+template <typename C, int W, int A = 1>
+__device__ __forceinline__ void relax_pairs(C (*h)[W], int c, C base, C ux, C uy, C uz, C omc, C ow1, C ow2) {
+  const C ow = wgt<C>(A) == wgt<C>(1) ? ow1 : ow2;  // omega w_A
+  C t = C(0);
+  if constexpr (ex(A) != 0) t += ex(A) > 0 ? ux : -ux;
+  if constexpr (ey(A) != 0) t += ey(A) > 0 ? uy : -uy;
+  if constexpr (ez(A) != 0) t += ez(A) > 0 ? uz : -uz;
+  const C even = ow * (base + C(4.5) * t * t);
+  const C odd = (C(3) * ow) * t;
+  h[A][c] = omc * h[A][c] + (even + odd);
+  h[A + 1][c] = omc * h[A + 1][c] + (even - odd);
+  if constexpr (A + 2 < 19) relax_pairs<C, W, A + 2>(h, c, base, ux, uy, uz, omc, ow1, ow2);
 }
 
 // SRT collision of cell c in shifted form (rho0 = 1).
 template <typename C, int W>
 __device__ __forceinline__ void collide(C (*h)[W], int c, C om) {
-  C drho = C(0), ux = C(0), uy = C(0), uz = C(0);
+  C drho = h[0][c], ux = C(0), uy = C(0), uz = C(0);
 #pragma unroll
-  for (int a = 0; a < 19; ++a) {
-    drho += h[a][c];
-    if (ex(a)) ux += ex(a) > 0 ? h[a][c] : -h[a][c];
-    if (ey(a)) uy += ey(a) > 0 ? h[a][c] : -h[a][c];
-    if (ez(a)) uz += ez(a) > 0 ? h[a][c] : -h[a][c];
+  for (int a = 1; a < 19; a += 2) {  // opposite pairs (a, a + 1)
+    drho += h[a][c] + h[a + 1][c];
+    const C d = h[a][c] - h[a + 1][c];
+    if (ex(a)) ux += ex(a) > 0 ? d : -d;
+    if (ey(a)) uy += ey(a) > 0 ? d : -d;
+    if (ez(a)) uz += ez(a) > 0 ? d : -d;
   }
-  const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
-  relax<C, W>(h, c, drho, ux, uy, uz, usq, om);
+  const C base = drho - C(1.5) * (ux * ux + uy * uy + uz * uz);
+  const C omc = C(1) - om;
+  h[0][c] = omc * h[0][c] + (om * wgt<C>(0)) * base;
+  relax_pairs<C, W>(h, c, base, ux, uy, uz, omc, om * wgt<C>(1), om * wgt<C>(7));
 }
 
 template <typename S, int N, bool SIMPLE>
@@ -300,7 +329,7 @@ __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache&
   C h[19][W];
   uint32_t odd = 0;
   pull_all<S, N, SIMPLE>(a, sc, slot, i0, j, k, h, odd);
-  if (!SIMPLE && odd) fixups<S, N>(a, sc, slot, fl, i0, j, k, h);
+  if (!SIMPLE && odd) fixups<S, N>(a, sc, fl, i0, j, k, h);
   if (a.collide) {
     const C om = Form<S>::omega(a);
 #pragma unroll
@@ -389,22 +418,36 @@ __device__ __forceinline__ void shift_all_h8(int i0, uint32_t (*q)[4], const uin
   if constexpr (A + 1 < 19) shift_all_h8<N, A + 1>(i0, q, edge);
 }
 
+__device__ __forceinline__ void set_half(uint32_t& w, int hi, float v) {
+  w = hi ? ((w & 0xFFFFu) | (half_bits(v) << 16)) : ((w & 0xFFFF0000u) | half_bits(v));
+}
+
 template <int N, int A = 0>
-__device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl, int i0,
-                                          int j, int k, uint32_t (*q)[4]) {
+__device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& sc, uint32_t fl, int i0, int j, int k,
+                                          uint32_t (*q)[4]) {
   uint32_t co;
   const uint32_t spec = special_cells<N, 8, A>(sc, fl, i0, j, k, co);
-  if (spec) {
+  const uint32_t cs = spec & ~co;
+  if (cs) {
+    float v[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-      if ((spec >> c) & 1u) {
+      v[c] = Form<__half>::ld((cs >> c) & 1u ? coarse_source<__half, N, A>(a, sc, i0 + c, j, k)
+                                              : static_cast<const __half*>(a.cur));
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if ((cs >> c) & 1u) set_half(q[A][c >> 1], c & 1, v[c]);
+  }
+  if (co) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if ((co >> c) & 1u) {
         uint32_t& w = q[A][c >> 1];
         const float regular = c & 1 ? half_hi(w) : half_lo(w);
-        const float v = special_value<__half, N, A>(a, sc, slot, i0 + c, j, k, (co >> c) & 1u, regular);
-        w = c & 1 ? ((w & 0xFFFFu) | (half_bits(v) << 16)) : ((w & 0xFFFF0000u) | half_bits(v));
+        set_half(w, c & 1, coalesced_value<__half, N, A>(a, sc, i0 + c, j, k, regular));
       }
   }
-  if constexpr (A + 1 < 19) fixups_h8<N, A + 1>(a, sc, slot, fl, i0, j, k, q);
+  if constexpr (A + 1 < 19) fixups_h8<N, A + 1>(a, sc, fl, i0, j, k, q);
 }
 
 template <int N, bool SIMPLE>
@@ -417,7 +460,7 @@ __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCac
   uint32_t odd = 0;
   issue_all_h8<N, SIMPLE>(a, sc, slot, i0, j, k, q, edge, odd);
   shift_all_h8<N>(i0, q, edge);
-  if (!SIMPLE && odd) fixups_h8<N>(a, sc, slot, fl, i0, j, k, q);
+  if (!SIMPLE && odd) fixups_h8<N>(a, sc, fl, i0, j, k, q);
   if (a.collide) {
     const float om = a.omega;
 #pragma unroll
@@ -453,9 +496,14 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, SlotCache& sc, in
   const int item = a.work[w];
   const int slot = item / TPB;
   const int cell0 = (item - slot * TPB) * CELLS + int(threadIdx.x) * W;
-  if (threadIdx.x < 27) sc.nbr[threadIdx.x] = a.nbr[slot * 27 + threadIdx.x];
-  __syncthreads();
   const uint32_t fl = a.flags[slot];
+  for (int q = threadIdx.x; q < 27; q += blockDim.x) sc.nbr[q] = a.nbr[slot * 27 + q];
+  if (fl & kHasFine) {
+    const int row = a.fine_index[slot];
+    if (row < 0 && threadIdx.x == 0) atomicOr(a.err, kErrNoChild);
+    for (int q = threadIdx.x; q < 8 * 27; q += blockDim.x) sc.fine_nbr[q] = row < 0 ? -1 : a.fine_nbr[row * 216 + q];
+  }
+  __syncthreads();
   if (fl & kAllSameLevel)
     update_any<S, N, true>(a, sc, slot, fl, cell0);
   else
