@@ -228,13 +228,37 @@ __device__ __forceinline__ void pull_all(const SweepArgs& a, const SlotCache& sc
   shift_all<S, N>(i0, h, edge);
 }
 
+// The slot's neighbour table as two 27-bit masks: neighbours that are not
+// level-L blocks (bit d for table entry d < 0) and finer neighbours
+// (entry d == kNbrFine).  Read once per lane from LDS; the per-direction
+// tests below are then bit tests.
+struct NbrMasks {
+  uint32_t other;
+  uint32_t fine;
+};
+__device__ __forceinline__ NbrMasks nbr_masks(const SlotCache& sc) {
+  NbrMasks m{0u, 0u};
+#pragma unroll
+  for (int d = 0; d < 27; ++d) {
+    const int32_t v = sc.nbr[d];
+    m.other |= uint32_t(v < 0) << d;
+    m.fine |= uint32_t(v == kNbrFine) << d;
+  }
+  // the table is the workgroup's: make the masks wave-uniform (scalar)
+  m.other = uint32_t(__builtin_amdgcn_readfirstlane(int(m.other)));
+  m.fine = uint32_t(__builtin_amdgcn_readfirstlane(int(m.fine)));
+  return m;
+}
+
 // Cells of a lane whose direction-A source is not an ordinary level-L read:
 // bit c of the returned mask; bit c of `co` marks a coalesced pair, i.e.
 // x - e_A or (edge directions) one of its axis projections in region(L+1).
 template <int N, int W, int A>
-__device__ __forceinline__ uint32_t special_cells(const SlotCache& sc, uint32_t fl, int i0, int j, int k,
-                                                  uint32_t& co) {
+__device__ __forceinline__ uint32_t special_cells(NbrMasks m, uint32_t fl, int i0, int j, int k, uint32_t& co) {
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  // keep each direction's tests next to its use (an empty asm on the scalar
+  // masks stops the compiler from evaluating all 19 directions up front)
+  asm volatile("" : "+s"(m.other), "+s"(m.fine));
   const int oy = EY == 0 ? 0 : side<N>(j - EY);
   const int oz = EZ == 0 ? 0 : side<N>(k - EZ);
   uint32_t spec = 0;
@@ -242,18 +266,18 @@ __device__ __forceinline__ uint32_t special_cells(const SlotCache& sc, uint32_t 
 #pragma unroll
   for (int c = 0; c < W; ++c) {
     const int ox = EX == 0 ? 0 : side<N>(i0 + c - EX);
-    const int nb = sc.nbr[13 + ox + 3 * oy + 9 * oz];
-    bool coal = false;
+    const int d = 13 + ox + 3 * oy + 9 * oz;
+    uint32_t coal = 0;
     if (fl & kHasFine) {
-      coal = nb == kNbrFine;
+      coal = (m.fine >> d) & 1u;
       if (A >= 7) {
         const int dA = EX != 0 ? 13 + ox : 13 + 3 * oy;
         const int dB = EZ != 0 ? 13 + 9 * oz : 13 + 3 * oy;
-        coal = coal || sc.nbr[dA] == kNbrFine || sc.nbr[dB] == kNbrFine;
+        coal |= ((m.fine >> dA) | (m.fine >> dB)) & 1u;
       }
     }
-    spec |= uint32_t(coal || nb < 0) << c;
-    co |= uint32_t(coal) << c;
+    spec |= (coal | ((m.other >> d) & 1u)) << c;
+    co |= coal << c;
   }
   return spec;
 }
@@ -261,12 +285,12 @@ __device__ __forceinline__ uint32_t special_cells(const SlotCache& sc, uint32_t 
 // Special sources of direction A for the W cells of a lane: the coarse
 // sources' loads are issued together, then the coalesced cells one by one.
 template <typename S, int N, int A = 0>
-__device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, uint32_t fl, int i0, int j, int k,
-                                       typename Form<S>::C (*h)[Geo<S, N>::W]) {
+__device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, const NbrMasks& m, uint32_t fl, int i0,
+                                       int j, int k, typename Form<S>::C (*h)[Geo<S, N>::W]) {
   using C = typename Form<S>::C;
   constexpr int W = Geo<S, N>::W;
   uint32_t co;
-  const uint32_t spec = special_cells<N, W, A>(sc, fl, i0, j, k, co);
+  const uint32_t spec = special_cells<N, W, A>(m, fl, i0, j, k, co);
   const uint32_t cs = spec & ~co;
   if (cs) {
     C v[W];
@@ -282,7 +306,7 @@ __device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, 
     for (int c = 0; c < W; ++c)
       if ((co >> c) & 1u) h[A][c] = coalesced_value<S, N, A>(a, sc, i0 + c, j, k, h[A][c]);
   }
-  if constexpr (A + 1 < 19) fixups<S, N, A + 1>(a, sc, fl, i0, j, k, h);
+  if constexpr (A + 1 < 19) fixups<S, N, A + 1>(a, sc, m, fl, i0, j, k, h);
 }
 
 // Relaxation of the opposite pair (A, A + 1), e_{A+1} = -e_A: with
@@ -329,7 +353,7 @@ __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache&
   C h[19][W];
   uint32_t odd = 0;
   pull_all<S, N, SIMPLE>(a, sc, slot, i0, j, k, h, odd);
-  if (!SIMPLE && odd) fixups<S, N>(a, sc, fl, i0, j, k, h);
+  if (!SIMPLE && odd) fixups<S, N>(a, sc, nbr_masks(sc), fl, i0, j, k, h);
   if (a.collide) {
     const C om = Form<S>::omega(a);
 #pragma unroll
@@ -423,10 +447,10 @@ __device__ __forceinline__ void set_half(uint32_t& w, int hi, float v) {
 }
 
 template <int N, int A = 0>
-__device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& sc, uint32_t fl, int i0, int j, int k,
-                                          uint32_t (*q)[4]) {
+__device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& sc, const NbrMasks& m, uint32_t fl,
+                                          int i0, int j, int k, uint32_t (*q)[4]) {
   uint32_t co;
-  const uint32_t spec = special_cells<N, 8, A>(sc, fl, i0, j, k, co);
+  const uint32_t spec = special_cells<N, 8, A>(m, fl, i0, j, k, co);
   const uint32_t cs = spec & ~co;
   if (cs) {
     float v[8];
@@ -447,7 +471,7 @@ __device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& s
         set_half(w, c & 1, coalesced_value<__half, N, A>(a, sc, i0 + c, j, k, regular));
       }
   }
-  if constexpr (A + 1 < 19) fixups_h8<N, A + 1>(a, sc, fl, i0, j, k, q);
+  if constexpr (A + 1 < 19) fixups_h8<N, A + 1>(a, sc, m, fl, i0, j, k, q);
 }
 
 template <int N, bool SIMPLE>
@@ -460,7 +484,7 @@ __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCac
   uint32_t odd = 0;
   issue_all_h8<N, SIMPLE>(a, sc, slot, i0, j, k, q, edge, odd);
   shift_all_h8<N>(i0, q, edge);
-  if (!SIMPLE && odd) fixups_h8<N>(a, sc, fl, i0, j, k, q);
+  if (!SIMPLE && odd) fixups_h8<N>(a, sc, nbr_masks(sc), fl, i0, j, k, q);
   if (a.collide) {
     const float om = a.omega;
 #pragma unroll
