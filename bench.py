@@ -75,11 +75,15 @@ def timed_steps(torch, g, stream, steps):
     return start.elapsed_time(end) / steps
 
 
-def level_table(g, sweeps, s_bytes):
-    """Mean launch time and algorithmic GB/s of every (level, substep)."""
-    return {f"L{L}s{s}": {"ms": round(m, 4), "launches": c, "cells": g.num_cells(L),
-                          "GBps": round(38 * s_bytes * g.num_cells(L) / (m * 1e-3) / 1e9, 1)}
-            for (L, s), (m, c) in sorted(sweeps.items())}
+def level_table(g, sweeps, s_bytes, coal=None):
+    """Mean launch time and algorithmic GB/s of every (level, substep), and
+    the mean time of each level's coalescence launch."""
+    out = {f"L{L}s{s}": {"ms": round(m, 4), "launches": c, "cells": g.num_cells(L),
+                         "GBps": round(38 * s_bytes * g.num_cells(L) / (m * 1e-3) / 1e9, 1)}
+           for (L, s), (m, c) in sorted(sweeps.items())}
+    for L, (m, c) in sorted((coal or {}).items()):
+        out[f"L{L}coalesce"] = {"ms": round(m, 4), "launches": c}
+    return out
 
 
 def launch_table(res):
@@ -169,7 +173,7 @@ def main():
     value = upd / (ms * 1e-3) / 1e6
 
     # dominant kernel: the finest-level sweep (77.6 M cells, 8 launches per step)
-    sweeps = g.time_sweeps(2)
+    sweeps, coal = g.time_launches(2)
     Lf = g.num_levels - 1
     fin = [sweeps[k] for k in sweeps if k[0] == Lf]
     fin_ms = sum(m * c for m, c in fin) / sum(c for _, c in fin)
@@ -178,7 +182,7 @@ def main():
     alg_bytes = 38 * s_bytes * nf          # 19 PDFs read + 19 written per interior cell
     achieved = alg_bytes / (fin_ms * 1e-3) / 1e9
     traffic = measured_traffic("f32", nf, fin_ms)
-    per_level = level_table(g, sweeps, s_bytes)
+    per_level = level_table(g, sweeps, s_bytes, coal)
     g.close()
     del g
     torch.cuda.synchronize()
@@ -192,9 +196,10 @@ def main():
         M16a, _ = g16.mass()
         ms16 = timed_steps(torch, g16, stream, max(3, args.steps // 2))
         M16b, _ = g16.mass()
+        sw16, co16 = g16.time_launches(2)
         forms["f16_graph"] = {"MLUPS": round(upd / (ms16 * 1e-3) / 1e6, 1), "ms_per_step": round(ms16, 3),
                               "roofline_MLUPS": round(HBM_PEAK_GBS * 1e9 / (38 * 2) / 1e6, 1),
-                              "per_level": level_table(g16, g16.time_sweeps(2), 2),
+                              "per_level": level_table(g16, sw16, 2, co16),
                               "launch": launch_table(launch16), "mass_drift": abs(M16b - M16a) / M16a}
         g16.close()
         del g16

@@ -204,6 +204,13 @@ int lbm_regrid(lbm_forest *f, const int8_t *flags, int64_t count);
  * L < num_levels, s in {1, 2} (level 0 only has s = 1).  Synchronizes. */
 int lbm_time_sweeps(lbm_forest *f, int n_steps, double *ms, int64_t *launches);
 
+/* The same, also timing the coalescence launches (one before each sweep of
+ * a level with finer neighbours): coal_ms[L], coal_launches[L] for
+ * L < num_levels (0 where there is none).  coal_ms and coal_launches are
+ * both given or both NULL. */
+int lbm_time_launches(lbm_forest *f, int n_steps, double *ms, int64_t *launches, double *coal_ms,
+                      int64_t *coal_launches);
+
 /* Wait for all work enqueued by this forest. */
 int lbm_synchronize(lbm_forest *f);
 

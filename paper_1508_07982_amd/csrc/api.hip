@@ -129,6 +129,15 @@ int make_levels(int n, size_t s, const std::vector<LevelTables>& tabs, std::vect
     if ((rc = upload(v.allocs, &v.flags, t.flags))) return rc;
     if ((rc = upload(v.allocs, &v.fine_index, t.fine_index))) return rc;
     if ((rc = upload(v.allocs, &v.fine_nbr, t.fine_nbr))) return rc;
+    if ((rc = upload(v.allocs, &v.fine_slot, t.fine_slot))) return rc;
+    if ((rc = upload(v.allocs, &v.pairs, t.coal_pairs))) return rc;
+    if ((rc = upload(v.allocs, &v.chunks, t.coal_chunks))) return rc;
+    v.nchunks = int32_t(t.coal_chunks.size() / 3);
+    if (v.nchunks) {
+      uint8_t* p = nullptr;
+      if ((rc = dev_alloc(v.allocs, &p, size_t(t.fine_blocks) * 19 * n3 * s))) return rc;
+      v.coal = p;
+    }
     if ((rc = upload(v.allocs, &v.work, t.work))) return rc;
   }
   return LBM_OK;
@@ -193,10 +202,27 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   a.nbr = d.nbr;
   a.flags = d.flags;
   a.fine_index = d.fine_index;
-  a.fine_nbr = d.fine_nbr;
+  a.coal = d.coal;
   a.omega = float(d.omega);
   a.omega64 = d.omega;
   a.err = f->d_err;
+  if (L + 1 < nlev && d.nchunks > 0) {
+    Op c;
+    c.level = L;
+    c.kind = Op::kCoalesce;
+    c.args = a;
+    c.coal.cur = cur;
+    c.coal.fine0 = fine0;
+    c.coal.fine1 = fine1;
+    c.coal.out = d.coal;
+    c.coal.pairs = d.pairs;
+    c.coal.chunks = d.chunks;
+    c.coal.nchunks = d.nchunks;
+    c.coal.nbr = d.nbr;
+    c.coal.fine_nbr = d.fine_nbr;
+    c.coal.fine_slot = d.fine_slot;
+    ops.push_back(c);
+  }
   ops.push_back(op);
   if (L == 0)
     r[0] ^= 1;
@@ -235,6 +261,10 @@ int apply_order(lbm_forest* f, int L) {
 
 int run_ops(lbm_forest* f, const std::vector<Op>& ops, bool per_block) {
   for (const Op& op : ops) {
+    if (op.kind == Op::kCoalesce) {
+      HIP_TRY(launch_coalesce(f->storage, f->n, op.coal, f->stream));
+      continue;
+    }
     if (op.args.nwork <= 0) continue;
     if (!per_block) {
       HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.level, op.args.nwork), f->stream));
@@ -679,12 +709,19 @@ int lbm_step_coarse(lbm_forest* f, int n_steps) {
 }
 
 int lbm_time_sweeps(lbm_forest* f, int n_steps, double* ms, int64_t* launches) {
-  if (!f || !ms || !launches) return fail(LBM_E_INVALID, "null pointer");
+  return lbm_time_launches(f, n_steps, ms, launches, nullptr, nullptr);
+}
+
+int lbm_time_launches(lbm_forest* f, int n_steps, double* ms, int64_t* launches, double* coal_ms,
+                      int64_t* coal_launches) {
+  if (!f || !ms || !launches || (!coal_ms) != (!coal_launches)) return fail(LBM_E_INVALID, "null pointer");
   if (n_steps < 1) return fail(LBM_E_INVALID, "n_steps < 1");
   if (!f->omega_set) return fail(LBM_E_STATE, "lbm_set_level_omega must be called first");
   HIP_TRY(hipSetDevice(f->device));
   const size_t nl = f->lv.size();
-  std::vector<std::pair<size_t, hipEvent_t>> marks;  // (level * 2 + substep - 1, start event), end follows
+  // (slot, start event), the end event follows in `ends`; slot level * 2 + substep - 1 for a
+  // sweep, 2 * levels + level for a coalescence
+  std::vector<std::pair<size_t, hipEvent_t>> marks;
   std::vector<hipEvent_t> ends;
   auto cleanup = [&]() {
     for (auto& m : marks) (void)hipEventDestroy(m.second);
@@ -698,31 +735,41 @@ int lbm_time_sweeps(lbm_forest* f, int n_steps, double* ms, int64_t* launches) {
       f->rot_prev = f->rot;
       f->steps_since_state++;
       for (const Op& op : ops) {
-        if (op.args.nwork <= 0) continue;
+        const bool coal = op.kind == Op::kCoalesce;
+        if (!coal && op.args.nwork <= 0) continue;
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
-        marks.emplace_back(size_t(op.level) * 2 + size_t(op.args.substep - 1), e0);
+        marks.emplace_back(coal ? 2 * nl + size_t(op.level) : size_t(op.level) * 2 + size_t(op.args.substep - 1), e0);
         HIP_TRY(hipEventCreate(&e1));
         ends.push_back(e1);
         HIP_TRY(hipEventRecord(e0, f->stream));
-        HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.level, op.args.nwork), f->stream));
+        if (coal)
+          HIP_TRY(launch_coalesce(f->storage, f->n, op.coal, f->stream));
+        else
+          HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.level, op.args.nwork), f->stream));
         HIP_TRY(hipEventRecord(e1, f->stream));
       }
       f->rot = r;
     }
     HIP_TRY(hipStreamSynchronize(f->stream));
-    for (size_t i = 0; i < 2 * nl; ++i) {
-      ms[i] = 0.0;
-      launches[i] = 0;
-    }
+    std::vector<double> tsum(3 * nl, 0.0);
+    std::vector<int64_t> tcnt(3 * nl, 0);
     for (size_t i = 0; i < marks.size(); ++i) {
       float t = 0.f;
       HIP_TRY(hipEventElapsedTime(&t, marks[i].second, ends[i]));
-      ms[marks[i].first] += t;
-      launches[marks[i].first] += 1;
+      tsum[marks[i].first] += t;
+      tcnt[marks[i].first] += 1;
     }
-    for (size_t i = 0; i < 2 * nl; ++i)
-      if (launches[i]) ms[i] /= double(launches[i]);
+    for (size_t i = 0; i < 3 * nl; ++i) {
+      const double mean = tcnt[i] ? tsum[i] / double(tcnt[i]) : 0.0;
+      if (i < 2 * nl) {
+        ms[i] = mean;
+        launches[i] = tcnt[i];
+      } else if (coal_ms) {
+        coal_ms[i - 2 * nl] = mean;
+        coal_launches[i - 2 * nl] = tcnt[i];
+      }
+    }
     return LBM_OK;
   };
   int rc = body();
@@ -785,9 +832,12 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
           for (int t = 0; t < tpb; ++t) work.push_back(b * tpb + t);
       if (work.empty()) continue;
       const Op* last = nullptr;
+      const Op* last_coal = nullptr;
       for (const Op& op : ops)
-        if (op.level == L) last = &op;
+        if (op.level == L) (op.kind == Op::kCoalesce ? last_coal : last) = &op;
       if (!last) return fail(LBM_E_STATE, "no launch recorded for level %d", L);
+      // the coalesced values of that launch, recomputed from the same buffers
+      if (last_coal) HIP_TRY(launch_coalesce(f->storage, n, last_coal->coal, f->stream));
       uint8_t* tmp = nullptr;
       int32_t* dwork = nullptr;
       int rc2;

@@ -356,6 +356,7 @@ int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>
         // neighbour tables of the 8 virtual level-(L+1) blocks of this block
         const int row = t.fine_blocks++;
         t.fine_index[s] = row;
+        t.fine_slot.push_back(s);
         t.fine_nbr.resize(size_t(row + 1) * 8 * 27, -1);
         for (int o = 0; o < 8; ++o) {
           const int vx = 2 * l.x + (o & 1), vy = 2 * l.y + ((o >> 1) & 1), vz = 2 * l.z + (o >> 2);
@@ -371,23 +372,34 @@ int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>
     for (size_t w = 0; w < t.work.size(); ++w) t.work[w] = int32_t(w);
   }
 
-  // coalesced (cell, direction) pairs, for reporting only: (X, a) is
-  // coalesced if X - e_a, or for an edge direction one of its two axis
-  // projections, lies in region(L+1).  Whether X - e_a leaves the block
-  // along an axis depends only on whether X sits on the low face, inside
-  // or on the high face along that axis, so cells are counted in those
-  // 27 position classes.
+  // coalesced (cell, direction) pairs: (X, a) is coalesced if X - e_a, or
+  // for an edge direction one of its two axis projections, lies in
+  // region(L+1).  Only cells on the block's boundary layer can be (their
+  // source leaves the block); the list is ordered by row, direction, cell,
+  // so that neighbouring threads of the coalescence read neighbouring cells.
+  // Whether (X, a) is coalesced depends only on X's position class (low
+  // face, inside or high face along each axis) and a.
+  std::vector<int> boundary, bclass;  // cells of the block's outer layer, ascending, and their class
+  for (int c = 0; c < n3; ++c) {
+    const int ijk[3] = {c % n, (c / n) % n, c / (n * n)};
+    int cls = 0;
+    for (int ax = 2; ax >= 0; --ax) cls = 3 * cls + (ijk[ax] == 0 ? 0 : (ijk[ax] == n - 1 ? 2 : 1));
+    if (cls != 13) {
+      boundary.push_back(c);
+      bclass.push_back(cls);
+    }
+  }
   for (int L = 0; L + 1 < nlev; ++L) {
     LevelTables& t = out[L];
     int64_t pairs = 0;
-    auto class_cells = [n](int c) -> int64_t { return c == 1 ? (n - 2) : 1; };  // 0 low, 1 inside, 2 high
     for (int s = 0; s < t.nblocks; ++s) {
       if (!(t.flags[s] & kHasFine)) continue;
+      const int row = t.fine_index[s];
+      const int64_t first = int64_t(t.coal_pairs.size());
+      uint32_t dirs[27];  // per class: bit a set if (X, a) is coalesced
       for (int cls = 0; cls < 27; ++cls) {
         const int pc[3] = {cls % 3, (cls / 3) % 3, cls / 9};
-        const int64_t cells = class_cells(pc[0]) * class_cells(pc[1]) * class_cells(pc[2]);
-        if (!cells) continue;
-        int64_t dirs = 0;
+        dirs[cls] = 0;
         for (int a = 1; a < 19; ++a) {
           int o[3];
           for (int ax = 0; ax < 3; ++ax) {
@@ -406,9 +418,20 @@ int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>
             const int di = (d[0] + 1) + 3 * (d[1] + 1) + 9 * (d[2] + 1);
             if (di != kNbrSelf && t.nbr[size_t(s) * 27 + di] == kNbrFine) coal = true;
           }
-          dirs += coal;
+          if (coal) dirs[cls] |= 1u << a;
         }
-        pairs += dirs * cells;
+      }
+      for (int a = 1; a < 19; ++a)
+        for (size_t q = 0; q < boundary.size(); ++q)
+          if ((dirs[bclass[q]] >> a) & 1u) {
+            t.coal_pairs.push_back((uint32_t(a) << 16) | uint32_t(boundary[q]));
+            ++pairs;
+          }
+      const int64_t end = int64_t(t.coal_pairs.size());
+      for (int64_t b = first; b < end; b += kCoalChunk) {
+        t.coal_chunks.push_back(row);
+        t.coal_chunks.push_back(int32_t(b));
+        t.coal_chunks.push_back(int32_t(std::min<int64_t>(end, b + kCoalChunk)));
       }
     }
     t.coalesced_pairs = pairs;

@@ -79,6 +79,8 @@ class Forest {
 };
 
 // Tables of one level, ready to copy to the device.
+constexpr int kCoalChunk = 256;  // coalesced pairs per chunk (one workgroup of the coalescence, a pair per thread)
+
 struct LevelTables {
   int level = 0;
   int n = 0;
@@ -91,6 +93,11 @@ struct LevelTables {
   std::vector<int32_t> fine_nbr;      // [row][octant][27]: level-(L+1) slot of the block at offset d
                                       // from the virtual level-(L+1) block (2 b + octant), or -1
   std::vector<int32_t> work;          // slot * tiles_per_block + tile
+  std::vector<int32_t> fine_slot;     // [row]: the slot whose fine_nbr row it is
+  std::vector<uint32_t> coal_pairs;   // coalesced (cell, direction) pairs by fine_nbr row:
+                                      // (direction << 16) | cell
+  std::vector<int32_t> coal_chunks;   // [chunk][3]: fine_nbr row, first pair, end pair (at most
+                                      // kCoalChunk pairs of one row each)
   int64_t coarse_blocks = 0;          // blocks touching level L-1
   int64_t fine_blocks = 0;            // blocks touching level L+1
   int64_t coalesced_pairs = 0;

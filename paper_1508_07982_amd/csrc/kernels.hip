@@ -167,6 +167,73 @@ __global__ void remap_kernel(RemapArgs a) {
   for (int d = 0; d < 19; ++d) Form<S>::st(out + pdf_at<N>(d, idx), h[d]);
 }
 
+// Neighbour offset (-1, 0, +1) of a local coordinate after a shift.
+template <int N>
+__device__ __forceinline__ int nb_side(int c) {
+  return c < 0 ? -1 : (c >= N ? 1 : 0);
+}
+
+// Coalesced pairs (X, a) of one chunk of one fine_nbr row per workgroup,
+// the row's neighbour tables in LDS: the mean over the 8 children c of X of
+// what the finer level's second stream pulled into c from c - e_a -- the
+// fine state after its first substep if c - e_a is a level-(L+1) cell, else
+// (c - e_a a halo cell, filled from c - 2 e_a in the first substep) the fine
+// state at the start of the parent step if c - 2 e_a is a level-(L+1) cell,
+// else the exploded coarse value, which is X's own source value at X - e_a
+// (eq. ftoc, Algorithm 1).  Children are summed in (z, y, x) order.
+constexpr int kCoalThreads = 256;
+
+template <typename S, int N>
+__global__ void __launch_bounds__(kCoalThreads) coalesce_kernel(CoalArgs c) {
+  using C = typename Form<S>::C;
+  constexpr int H = N / 2;
+  __shared__ int32_t fns[8 * 27];
+  __shared__ int32_t nbs[27];
+  const int row = c.chunks[3 * blockIdx.x], first = c.chunks[3 * blockIdx.x + 1], end = c.chunks[3 * blockIdx.x + 2];
+  const int slot = c.fine_slot[row];
+  for (int q = threadIdx.x; q < 8 * 27; q += blockDim.x) fns[q] = c.fine_nbr[int64_t(row) * 216 + q];
+  for (int q = threadIdx.x; q < 27; q += blockDim.x) nbs[q] = c.nbr[int64_t(slot) * 27 + q];
+  __syncthreads();
+  for (int t = first + int(threadIdx.x); t < end; t += blockDim.x) {
+    const uint32_t w = c.pairs[t];
+    const int A = int(w >> 16), cell = int(w & 0xFFFFu);
+    const int i = cell % N, j = (cell / N) % N, k = cell / (N * N);
+    const int EX = ex(A), EY = ey(A), EZ = ez(A);
+    const int sx = i - EX, sy = j - EY, sz = k - EZ;
+    const int nb = nbs[13 + nb_side<N>(sx) + 3 * nb_side<N>(sy) + 9 * nb_side<N>(sz)];
+    const S* rp = nb >= 0 ? static_cast<const S*>(c.cur) +
+                                pdf_index<N>(A, uint32_t(nb), uint32_t((sx & (N - 1)) + N * ((sy & (N - 1)) +
+                                                                                             N * (sz & (N - 1)))))
+                          : static_cast<const S*>(c.cur);
+    const int oct = (i >= H ? 1 : 0) | (j >= H ? 2 : 0) | (k >= H ? 4 : 0);
+    const int32_t* fn = fns + oct * 27;
+    const int cx = 2 * (i & (H - 1)), cy = 2 * (j & (H - 1)), cz = 2 * (k & (H - 1));
+    C v[8];
+    bool fine[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int yx = cx + (q & 1) - EX, yy = cy + ((q >> 1) & 1) - EY, yz = cz + (q >> 2) - EZ;
+      const int fy = fn[13 + nb_side<N>(yx) + 3 * nb_side<N>(yy) + 9 * nb_side<N>(yz)];
+      const int zx = yx - EX, zy = yy - EY, zz = yz - EZ;
+      const int fz = fn[13 + nb_side<N>(zx) + 3 * nb_side<N>(zy) + 9 * nb_side<N>(zz)];
+      const S* p = fy >= 0 ? static_cast<const S*>(c.fine1) +
+                                 pdf_index<N>(A, uint32_t(fy), uint32_t((yx & (N - 1)) + N * ((yy & (N - 1)) +
+                                                                                              N * (yz & (N - 1)))))
+                   : fz >= 0 ? static_cast<const S*>(c.fine0) +
+                                   pdf_index<N>(A, uint32_t(fz), uint32_t((zx & (N - 1)) + N * ((zy & (N - 1)) +
+                                                                                                N * (zz & (N - 1)))))
+                             : static_cast<const S*>(c.cur);
+      fine[q] = fy >= 0 || fz >= 0;
+      v[q] = Form<S>::ld(p);
+    }
+    const C regular = nb >= 0 ? C(Form<S>::ld(rp)) : C(0);
+    C sum = C(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sum += fine[q] ? v[q] : regular;
+    Form<S>::st(static_cast<S*>(c.out) + pdf_index<N>(A, uint32_t(row), uint32_t(cell)), sum * C(0.125));
+  }
+}
+
 template <typename F>
 hipError_t dispatch(int storage, int n, F&& f) {
   auto by_n = [&](auto tag) -> hipError_t {
@@ -261,6 +328,16 @@ hipError_t launch_remap(int storage, int n, const RemapArgs& a, hipStream_t stre
     using S = decltype(s);
     constexpr int N = decltype(nn)::value;
     hipLaunchKernelGGL((remap_kernel<S, N>), dim3(grid_for(a.ncells, 256)), dim3(256), 0, stream, a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_coalesce(int storage, int n, const CoalArgs& a, hipStream_t stream) {
+  if (a.nchunks <= 0) return hipSuccess;
+  return dispatch(storage, n, [&](auto s, auto nn) {
+    using S = decltype(s);
+    constexpr int N = decltype(nn)::value;
+    hipLaunchKernelGGL((coalesce_kernel<S, N>), dim3(a.nchunks), dim3(kCoalThreads), 0, stream, a);
     return hipGetLastError();
   });
 }

@@ -25,13 +25,34 @@ struct SweepArgs {
   const int32_t* nbr;         // [slot][27]
   const uint32_t* flags;      // [slot]
   const int32_t* fine_index;  // [slot]
-  const int32_t* fine_nbr;    // [row][8][27]
+  const void* coal;           // coalesced values of this substep, [row][19][n^3] (see CoalArgs)
   float omega;                // omega_L (FP32 arithmetic forms)
   double omega64;             // omega_L (FP64 form)
   int* err;                   // error bits (table lookup failures)
 };
 
 enum ErrBits : int { kErrNoSource = 1, kErrNoChild = 2 };
+
+// Coalescence of level L for one of its substeps (eq. ftoc), run after the
+// finer level's two substeps and before the level-L sweep: for every
+// coalesced pair (X, a) of a slot with finer neighbours, the mean over the 8
+// children of X of what the finer level's second stream pulled into them,
+// written to out[row][a][cell] (block-major like the state, one block per
+// fine_nbr row).
+struct CoalArgs {
+  const void* cur;            // level-L state read by the following sweep (the regular sources)
+  const void* fine0;          // level-(L+1) state at the start of the parent step
+  const void* fine1;          // level-(L+1) state after its first substep
+  void* out;                  // [row][19][n^3]
+  const uint32_t* pairs;      // [pair]: (direction << 16) | cell, grouped by row
+  const int32_t* chunks;      // [chunk][3]: row, first pair, end pair
+  int32_t nchunks;
+  const int32_t* nbr;         // level-L [slot][27]
+  const int32_t* fine_nbr;    // [row][8][27]
+  const int32_t* fine_slot;   // [row]
+};
+
+hipError_t launch_coalesce(int storage, int n, const CoalArgs& a, hipStream_t stream);
 
 // Cells per work tile of the sweep kernel (one workgroup's share).
 int sweep_tile_cells(int storage, int n);

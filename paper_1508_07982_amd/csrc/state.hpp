@@ -25,6 +25,11 @@ struct LevelDev {
   uint32_t* flags = nullptr;
   int32_t* fine_index = nullptr;
   int32_t* fine_nbr = nullptr;
+  int32_t* fine_slot = nullptr;
+  uint32_t* pairs = nullptr;    // coalesced pairs
+  int32_t* chunks = nullptr;    // coalescence work: row, first pair, end pair
+  int32_t nchunks = 0;
+  void* coal = nullptr;         // coalesced values [fine row][19][n^3]
   int32_t* work = nullptr;      // work tiles in canonical order
   int32_t* work_xcd = nullptr;  // the same tiles in XCD-grouped order (order 1), allocated on demand
   int persistent = -1;          // launch shape of this level; -1: the forest-wide setting
@@ -33,9 +38,14 @@ struct LevelDev {
   std::vector<void*> allocs;  // device memory owned by this level
 };
 
+// One launch of the coarse step: a level substep's sweep, or the
+// coalescence that precedes it on a level with finer neighbours.
 struct Op {
+  enum Kind { kSweep = 0, kCoalesce = 1 };
   int level;
+  int kind = kSweep;
   SweepArgs args;
+  CoalArgs coal;
 };
 
 }  // namespace lbm

@@ -40,11 +40,10 @@ namespace lbm {
 namespace dev {
 
 // Per-workgroup copy of the slot's neighbour table and, for a slot with
-// finer neighbours, of the neighbour tables of its 8 virtual level-(L+1)
-// blocks (octant-major).
+// finer neighbours, its row in the coalesced-value buffer.
 struct SlotCache {
   int32_t nbr[27];
-  int32_t fine_nbr[8 * 27];
+  int32_t fine_row;
 };
 
 // Neighbour offset (-1, 0, +1) of a local coordinate after a shift.
@@ -98,47 +97,12 @@ __device__ __forceinline__ const S* coarse_source(const SweepArgs& a, const Slot
   return parent_ptr<S, N, A>(a, cz, zx & (N - 1), zy & (N - 1), zz & (N - 1));
 }
 
-// Coalescence (eq. ftoc): the mean over the 8 children c of the cell of the
-// value the child holds after the finer level's two substeps, i.e. what the
-// second fine stream pulled into c from c - e_A:
-//   c - e_A in a level-(L+1) block  -> that cell's state after substep 1;
-//   otherwise c - e_A is a halo cell, whose first-substep value came from
-//   c - 2 e_A: the fine state at t if that is a level-(L+1) cell, else the
-//   exploded coarse value, which is this cell's ordinary source `regular`.
-// The 8 loads carry no branch (a child without a fine source loads a dummy
-// address and takes `regular`), so they are in flight together.
+// Coalescence (eq. ftoc): the value of a coalesced pair comes from the
+// coalescence launch that precedes this sweep (see CoalArgs), stored like
+// the state at the slot's fine row.
 template <typename S, int N, int A>
-__device__ __forceinline__ typename Form<S>::C coalesced_value(const SweepArgs& a, const SlotCache& sc, int i, int j,
-                                                               int k, typename Form<S>::C regular) {
-  using C = typename Form<S>::C;
-  constexpr int H = Geo<S, N>::H;
-  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
-  const int oct = (i >= H ? 1 : 0) | (j >= H ? 2 : 0) | (k >= H ? 4 : 0);
-  const int32_t* fn = sc.fine_nbr + oct * 27;
-  const S* f1 = static_cast<const S*>(a.fine1);
-  const S* f0 = static_cast<const S*>(a.fine0);
-  const S* dummy = static_cast<const S*>(a.cur);
-  const int cx = 2 * (i & (H - 1)), cy = 2 * (j & (H - 1)), cz = 2 * (k & (H - 1));
-  C v[8];
-  bool fine[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int yx = cx + (q & 1) - EX, yy = cy + ((q >> 1) & 1) - EY, yz = cz + (q >> 2) - EZ;
-    const int fy = fn[13 + side<N>(yx) + 3 * side<N>(yy) + 9 * side<N>(yz)];
-    const int zx = yx - EX, zy = yy - EY, zz = yz - EZ;
-    const int fz = fn[13 + side<N>(zx) + 3 * side<N>(zy) + 9 * side<N>(zz)];
-    const S* p = fy >= 0 ? f1 + pdf_index<N>(A, uint32_t(fy), uint32_t((yx & (N - 1)) + N * ((yy & (N - 1)) +
-                                                                                          N * (yz & (N - 1)))))
-               : fz >= 0 ? f0 + pdf_index<N>(A, uint32_t(fz), uint32_t((zx & (N - 1)) + N * ((zy & (N - 1)) +
-                                                                                          N * (zz & (N - 1)))))
-                         : dummy;
-    fine[q] = fy >= 0 || fz >= 0;
-    v[q] = Form<S>::ld(p);
-  }
-  C s = C(0);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) s += fine[q] ? v[q] : regular;
-  return s * C(0.125);
+__device__ __forceinline__ const S* coalesced_source(const SweepArgs& a, const SlotCache& sc, int i, int j, int k) {
+  return static_cast<const S*>(a.coal) + pdf_index<N>(A, uint32_t(sc.fine_row), uint32_t(i + N * (j + N * k)));
 }
 
 // Index of direction A among the 10 directions with a nonzero x component.
@@ -282,8 +246,9 @@ __device__ __forceinline__ uint32_t special_cells(NbrMasks m, uint32_t fl, int i
   return spec;
 }
 
-// Special sources of direction A for the W cells of a lane: the coarse
-// sources' loads are issued together, then the coalesced cells one by one.
+// Special sources of direction A for the W cells of a lane (coarse sources
+// and coalesced pairs), addressed first and loaded together: one memory
+// round trip per direction.
 template <typename S, int N, int A = 0>
 __device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, const NbrMasks& m, uint32_t fl, int i0,
                                        int j, int k, typename Form<S>::C (*h)[Geo<S, N>::W]) {
@@ -291,20 +256,18 @@ __device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, 
   constexpr int W = Geo<S, N>::W;
   uint32_t co;
   const uint32_t spec = special_cells<N, W, A>(m, fl, i0, j, k, co);
-  const uint32_t cs = spec & ~co;
-  if (cs) {
+  if (spec) {
     C v[W];
 #pragma unroll
-    for (int c = 0; c < W; ++c)
-      v[c] = Form<S>::ld((cs >> c) & 1u ? coarse_source<S, N, A>(a, sc, i0 + c, j, k) : static_cast<const S*>(a.cur));
+    for (int c = 0; c < W; ++c) {
+      const S* p = !((spec >> c) & 1u) ? static_cast<const S*>(a.cur)
+                   : (co >> c) & 1u    ? coalesced_source<S, N, A>(a, sc, i0 + c, j, k)
+                                       : coarse_source<S, N, A>(a, sc, i0 + c, j, k);
+      v[c] = Form<S>::ld(p);
+    }
 #pragma unroll
     for (int c = 0; c < W; ++c)
-      if ((cs >> c) & 1u) h[A][c] = v[c];
-  }
-  if (co) {
-#pragma unroll
-    for (int c = 0; c < W; ++c)
-      if ((co >> c) & 1u) h[A][c] = coalesced_value<S, N, A>(a, sc, i0 + c, j, k, h[A][c]);
+      if ((spec >> c) & 1u) h[A][c] = v[c];
   }
   if constexpr (A + 1 < 19) fixups<S, N, A + 1>(a, sc, m, fl, i0, j, k, h);
 }
@@ -451,25 +414,18 @@ __device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& s
                                           int i0, int j, int k, uint32_t (*q)[4]) {
   uint32_t co;
   const uint32_t spec = special_cells<N, 8, A>(m, fl, i0, j, k, co);
-  const uint32_t cs = spec & ~co;
-  if (cs) {
+  if (spec) {
     float v[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-      v[c] = Form<__half>::ld((cs >> c) & 1u ? coarse_source<__half, N, A>(a, sc, i0 + c, j, k)
-                                              : static_cast<const __half*>(a.cur));
+    for (int c = 0; c < 8; ++c) {
+      const __half* p = !((spec >> c) & 1u) ? static_cast<const __half*>(a.cur)
+                        : (co >> c) & 1u    ? coalesced_source<__half, N, A>(a, sc, i0 + c, j, k)
+                                            : coarse_source<__half, N, A>(a, sc, i0 + c, j, k);
+      v[c] = Form<__half>::ld(p);
+    }
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-      if ((cs >> c) & 1u) set_half(q[A][c >> 1], c & 1, v[c]);
-  }
-  if (co) {
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-      if ((co >> c) & 1u) {
-        uint32_t& w = q[A][c >> 1];
-        const float regular = c & 1 ? half_hi(w) : half_lo(w);
-        set_half(w, c & 1, coalesced_value<__half, N, A>(a, sc, i0 + c, j, k, regular));
-      }
+      if ((spec >> c) & 1u) set_half(q[A][c >> 1], c & 1, v[c]);
   }
   if constexpr (A + 1 < 19) fixups_h8<N, A + 1>(a, sc, m, fl, i0, j, k, q);
 }
@@ -522,10 +478,10 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, SlotCache& sc, in
   const int cell0 = (item - slot * TPB) * CELLS + int(threadIdx.x) * W;
   const uint32_t fl = a.flags[slot];
   for (int q = threadIdx.x; q < 27; q += blockDim.x) sc.nbr[q] = a.nbr[slot * 27 + q];
-  if (fl & kHasFine) {
-    const int row = a.fine_index[slot];
-    if (row < 0 && threadIdx.x == 0) atomicOr(a.err, kErrNoChild);
-    for (int q = threadIdx.x; q < 8 * 27; q += blockDim.x) sc.fine_nbr[q] = row < 0 ? -1 : a.fine_nbr[row * 216 + q];
+  if (threadIdx.x == 0) {
+    const int row = fl & kHasFine ? a.fine_index[slot] : 0;
+    if (row < 0) atomicOr(a.err, kErrNoChild);
+    sc.fine_row = row < 0 ? 0 : row;
   }
   __syncthreads();
   if (fl & kAllSameLevel)

@@ -72,6 +72,8 @@ _SIGNATURES = {
     "lbm_set_launch": [ctypes.c_void_p, ctypes.c_int],
     "lbm_synchronize": [ctypes.c_void_p],
     "lbm_time_sweeps": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_time_launches": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_void_p],
     "lbm_regrid": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
     "lbm_block_indicators": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_mlp_create": [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)],
@@ -277,6 +279,18 @@ class Forest:
         cnt = np.zeros(2 * self.num_levels, dtype=np.int64)
         _check(self._lib.lbm_time_sweeps(self._h, int(n_steps), _ptr(ms), _ptr(cnt)))
         return {(i // 2, i % 2 + 1): (float(ms[i]), int(cnt[i])) for i in range(2 * self.num_levels) if cnt[i]}
+
+    def time_launches(self, n_steps: int = 1):
+        """As time_sweeps, plus {level: (mean ms, launches)} of the
+        coalescence launches."""
+        nl = self.num_levels
+        ms = np.zeros(2 * nl)
+        cnt = np.zeros(2 * nl, dtype=np.int64)
+        cms = np.zeros(nl)
+        ccnt = np.zeros(nl, dtype=np.int64)
+        _check(self._lib.lbm_time_launches(self._h, int(n_steps), _ptr(ms), _ptr(cnt), _ptr(cms), _ptr(ccnt)))
+        sweeps = {(i // 2, i % 2 + 1): (float(ms[i]), int(cnt[i])) for i in range(2 * nl) if cnt[i]}
+        return sweeps, {L: (float(cms[L]), int(ccnt[L])) for L in range(nl) if ccnt[L]}
 
     def regrid(self, flags):
         """Split (> 0), merge (< 0) or keep (0) every leaf (canonical order)."""
