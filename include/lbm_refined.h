@@ -167,21 +167,26 @@ int lbm_set_launch(lbm_forest *f, int persistent);
  * follow the forest-wide setting); order 0 sweeps the work tiles in
  * canonical order, order 1 groups them so that each of the 8 XCDs (to which
  * workgroups are dispatched round-robin) sweeps one contiguous range of
- * tiles.  Synchronizes the stream; invalidates captured graphs; kept across
- * lbm_regrid for levels that still exist.  Results do not depend on it. */
-int lbm_set_level_launch(lbm_forest *f, int level, int persistent, int order);
-int lbm_get_level_launch(const lbm_forest *f, int level, int *persistent, int *order);
+ * tiles; split (1, 2 or 4) sweeps each work tile with that many workgroups
+ * of 256 / split lanes (the largest allowed split <= the request is used:
+ * a workgroup keeps at least one full wavefront).  Synchronizes the stream;
+ * invalidates captured graphs; kept across lbm_regrid for levels that still
+ * exist.  Results do not depend on it. */
+int lbm_set_level_launch(lbm_forest *f, int level, int persistent, int order, int split);
+int lbm_get_level_launch(const lbm_forest *f, int level, int *persistent, int *order, int *split);
 
 /* Autotuner of the launch shape (the batching form: every level's tiles in
  * one launch per substep, the step captured as a graph).  Times each
- * candidate (persistent in {0, 1, 2, 4, 8}) x (order in {0, 1}) with
- * lbm_time_sweeps over one warm-up and n_steps >= 1 coarse steps, keeps for
- * every level the candidate with the smallest mean step time of that level,
- * and applies it.  result[3 * L + {0, 1, 2}] = chosen persistent, order and
- * that level's mean time per level step in ms.  The PDF state is saved
- * before and restored after (device memory equal to the forest's PDF
- * storage is allocated for it; LBM_E_OOM otherwise), so the simulation is
- * left exactly where it was.  Synchronizes. */
+ * candidate (persistent, order, split) -- one workgroup per work unit with
+ * order {0, 1} x split {1, 2, 4}, and persistent grids of {1, 2, 4, 8}
+ * workgroups per CU with order {0, 1} -- with lbm_time_sweeps over one
+ * warm-up and n_steps >= 1 coarse steps, keeps for every level the
+ * candidate with the smallest mean step time of that level, and applies it.
+ * result[4 * L + {0, 1, 2, 3}] = chosen persistent, order, split and that
+ * level's mean time per level step in ms.  The PDF state is saved before
+ * and restored after (device memory equal to the forest's PDF storage is
+ * allocated for it; LBM_E_OOM otherwise), so the simulation is left exactly
+ * where it was.  Synchronizes. */
 int lbm_autotune(lbm_forest *f, int n_steps, double *result);
 
 /* Dynamic regrid (the paper names dynamic refinement as future work; the

@@ -232,8 +232,14 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
 
 int grid_for(const lbm_forest* f, int level, int nwork) {
   const int p = f->lv[level].persistent >= 0 ? f->lv[level].persistent : f->persistent;
-  if (p <= 0) return nwork;
-  return std::max(1, std::min(nwork, f->num_cu * p));
+  const int units = nwork * f->lv[level].split;
+  if (p <= 0) return units;
+  return std::max(1, std::min(units, f->num_cu * p));
+}
+
+hipError_t launch_level(const lbm_forest* f, const Op& op) {
+  return launch_sweep(f->storage, f->n, op.args, grid_for(f, op.level, op.args.nwork), f->lv[op.level].split,
+                      f->stream);
 }
 
 // Tile order 1: workgroups are dispatched round-robin over the 8 XCDs
@@ -267,14 +273,14 @@ int run_ops(lbm_forest* f, const std::vector<Op>& ops, bool per_block) {
     }
     if (op.args.nwork <= 0) continue;
     if (!per_block) {
-      HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.level, op.args.nwork), f->stream));
+      HIP_TRY(launch_level(f, op));
     } else {
       const LevelDev& d = f->lv[op.level];
       for (int s = 0; s < d.nblocks; ++s) {
         SweepArgs a = op.args;
         a.work = d.work + size_t(s) * d.tiles_per_block;
         a.nwork = d.tiles_per_block;
-        HIP_TRY(launch_sweep(f->storage, f->n, a, a.nwork, f->stream));
+        HIP_TRY(launch_sweep(f->storage, f->n, a, a.nwork, 1, f->stream));
       }
     }
   }
@@ -579,26 +585,29 @@ int lbm_set_launch(lbm_forest* f, int persistent) {
   return LBM_OK;
 }
 
-int lbm_set_level_launch(lbm_forest* f, int level, int persistent, int order) {
+int lbm_set_level_launch(lbm_forest* f, int level, int persistent, int order, int split) {
   if (!f) return fail(LBM_E_INVALID, "null pointer");
   if (level < 0 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
   if (persistent < -1 || persistent > 64) return fail(LBM_E_INVALID, "persistent must lie in [-1, 64]");
   if (order != 0 && order != 1) return fail(LBM_E_INVALID, "order must be 0 or 1");
+  if (split != 1 && split != 2 && split != 4) return fail(LBM_E_INVALID, "split must be 1, 2 or 4");
   HIP_TRY(hipSetDevice(f->device));
   HIP_TRY(hipStreamSynchronize(f->stream));
   f->lv[level].persistent = persistent;
   f->lv[level].order = order;
+  f->lv[level].split = sweep_split(f->storage, f->n, split);
   int rc = apply_order(f, level);
   if (rc) return rc;
   invalidate_graphs(f);
   return LBM_OK;
 }
 
-int lbm_get_level_launch(const lbm_forest* f, int level, int* persistent, int* order) {
-  if (!f || !persistent || !order) return fail(LBM_E_INVALID, "null pointer");
+int lbm_get_level_launch(const lbm_forest* f, int level, int* persistent, int* order, int* split) {
+  if (!f || !persistent || !order || !split) return fail(LBM_E_INVALID, "null pointer");
   if (level < 0 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
   *persistent = f->lv[level].persistent;
   *order = f->lv[level].order;
+  *split = f->lv[level].split;
   return LBM_OK;
 }
 
@@ -629,16 +638,20 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
         HIP_TRY(hipMemcpyAsync(copy[L][b], v.buf[b], bytes, hipMemcpyDeviceToDevice, f->stream));
       }
     }
-    static const int kCand[][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {4, 0}, {4, 1}, {8, 0}, {8, 1}};
+    // (persistent, order, split); splits the storage form does not allow
+    // fall back to the largest allowed one
+    static const int kCand[][3] = {{0, 0, 1}, {0, 1, 1}, {0, 0, 2}, {0, 1, 2}, {0, 0, 4}, {0, 1, 4}, {1, 0, 1},
+                                   {1, 1, 1}, {2, 0, 1}, {2, 1, 1}, {4, 0, 1}, {4, 1, 1}, {8, 0, 1}, {8, 1, 1}};
     const int ncand = int(sizeof(kCand) / sizeof(kCand[0]));
     std::vector<double> best(nl, 1e300);
-    std::vector<int> bp(nl, 0), bo(nl, 0);
+    std::vector<int> bp(nl, 0), bo(nl, 0), bs(nl, 1);
     std::vector<double> ms(2 * nl);
     std::vector<int64_t> cnt(2 * nl);
     for (int c = 0; c < ncand; ++c) {
       for (int L = 0; L < nl; ++L) {
         f->lv[L].persistent = kCand[c][0];
         f->lv[L].order = kCand[c][1];
+        f->lv[L].split = sweep_split(f->storage, f->n, kCand[c][2]);
         if ((rc = apply_order(f, L))) return rc;
       }
       if ((rc = lbm_time_sweeps(f, 1, ms.data(), cnt.data()))) return rc;  // warm-up
@@ -650,16 +663,19 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
           best[L] = t;
           bp[L] = kCand[c][0];
           bo[L] = kCand[c][1];
+          bs[L] = f->lv[L].split;
         }
       }
     }
     for (int L = 0; L < nl; ++L) {
       f->lv[L].persistent = bp[L];
       f->lv[L].order = bo[L];
+      f->lv[L].split = bs[L];
       if ((rc = apply_order(f, L))) return rc;
-      result[3 * L] = bp[L];
-      result[3 * L + 1] = bo[L];
-      result[3 * L + 2] = best[L] < 1e300 ? best[L] : 0.0;
+      result[4 * L] = bp[L];
+      result[4 * L + 1] = bo[L];
+      result[4 * L + 2] = bs[L];
+      result[4 * L + 3] = best[L] < 1e300 ? best[L] : 0.0;
     }
     for (int L = 0; L < nl; ++L) {
       const LevelDev& v = f->lv[L];
@@ -746,7 +762,7 @@ int lbm_time_launches(lbm_forest* f, int n_steps, double* ms, int64_t* launches,
         if (coal)
           HIP_TRY(launch_coalesce(f->storage, f->n, op.coal, f->stream));
         else
-          HIP_TRY(launch_sweep(f->storage, f->n, op.args, grid_for(f, op.level, op.args.nwork), f->stream));
+          HIP_TRY(launch_level(f, op));
         HIP_TRY(hipEventRecord(e1, f->stream));
       }
       f->rot = r;
@@ -848,7 +864,7 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
       a.collide = 0;
       a.work = dwork;
       a.nwork = int32_t(work.size());
-      HIP_TRY(launch_sweep(f->storage, n, a, a.nwork, f->stream));
+      HIP_TRY(launch_sweep(f->storage, n, a, a.nwork, 1, f->stream));
       post[L] = tmp;
     }
     const void** d_cur = nullptr;
@@ -933,6 +949,7 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
     for (size_t L = 0; L < nlv.size() && L < f->lv.size(); ++L) {
       nlv[L].persistent = f->lv[L].persistent;
       nlv[L].order = f->lv[L].order;
+      nlv[L].split = f->lv[L].split;
     }
     free_levels(f->lv);
     f->lv = std::move(nlv);

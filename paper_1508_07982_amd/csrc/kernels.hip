@@ -12,9 +12,12 @@
 
 namespace lbm {
 
-hipError_t launch_sweep_f64(int n, const SweepArgs& a, int grid, hipStream_t stream);
-hipError_t launch_sweep_f32(int n, const SweepArgs& a, int grid, hipStream_t stream);
-hipError_t launch_sweep_f16(int n, const SweepArgs& a, int grid, hipStream_t stream);
+hipError_t launch_sweep_f64(int n, const SweepArgs& a, int grid, int split, hipStream_t stream);
+hipError_t launch_sweep_f32(int n, const SweepArgs& a, int grid, int split, hipStream_t stream);
+hipError_t launch_sweep_f16(int n, const SweepArgs& a, int grid, int split, hipStream_t stream);
+int sweep_split_f64(int n, int requested);
+int sweep_split_f32(int n, int requested);
+int sweep_split_f16(int n, int requested);
 
 namespace {
 using namespace dev;
@@ -264,12 +267,21 @@ int sweep_tile_cells(int storage, int n) {
   return n3 < 256 * w ? n3 : 256 * w;
 }
 
-hipError_t launch_sweep(int storage, int n, const SweepArgs& a, int grid, hipStream_t stream) {
+int sweep_split(int storage, int n, int requested) {
+  switch (storage) {
+    case 0: return sweep_split_f64(n, requested);
+    case 1: return sweep_split_f32(n, requested);
+    case 2: return sweep_split_f16(n, requested);
+    default: return 1;
+  }
+}
+
+hipError_t launch_sweep(int storage, int n, const SweepArgs& a, int grid, int split, hipStream_t stream) {
   if (a.nwork <= 0) return hipSuccess;
   switch (storage) {
-    case 0: return launch_sweep_f64(n, a, grid, stream);
-    case 1: return launch_sweep_f32(n, a, grid, stream);
-    case 2: return launch_sweep_f16(n, a, grid, stream);
+    case 0: return launch_sweep_f64(n, a, grid, split, stream);
+    case 1: return launch_sweep_f32(n, a, grid, split, stream);
+    case 2: return launch_sweep_f16(n, a, grid, split, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -57,8 +57,14 @@ hipError_t launch_coalesce(int storage, int n, const CoalArgs& a, hipStream_t st
 // Cells per work tile of the sweep kernel (one workgroup's share).
 int sweep_tile_cells(int storage, int n);
 
-// storage: 0 = f64, 1 = f32, 2 = f16
-hipError_t launch_sweep(int storage, int n, const SweepArgs& a, int grid, hipStream_t stream);
+// Workgroup split of the sweep: each work tile is swept by `split` (1, 2
+// or 4) workgroups of 1 / split of the lanes.  sweep_split returns the
+// largest split <= requested that keeps a full wavefront per workgroup.
+int sweep_split(int storage, int n, int requested);
+
+// storage: 0 = f64, 1 = f32, 2 = f16.  grid >= nwork * split launches one
+// workgroup per work unit; a smaller grid is persistent.
+hipError_t launch_sweep(int storage, int n, const SweepArgs& a, int grid, int split, hipStream_t stream);
 
 // The helpers below address the interior cells [0, ncells) of one level
 // (block-major buffer: element (a, slot, cell) at (19 slot + a) n^3 + cell).

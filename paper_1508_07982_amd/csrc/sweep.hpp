@@ -470,12 +470,15 @@ __device__ __forceinline__ void update_any(const SweepArgs& a, const SlotCache& 
     update_lane<S, N, SIMPLE>(a, sc, slot, fl, cell0);
 }
 
-template <typename S, int N>
+// Work unit w: part w % SPLIT of work tile w / SPLIT (a tile split into
+// SPLIT consecutive runs of whole rows, one per workgroup of T / SPLIT
+// lanes).
+template <typename S, int N, int SPLIT>
 __device__ __forceinline__ void sweep_item(const SweepArgs& a, SlotCache& sc, int w) {
   constexpr int W = Geo<S, N>::W, CELLS = Geo<S, N>::CELLS, TPB = Geo<S, N>::TPB;
-  const int item = a.work[w];
+  const int item = a.work[w / SPLIT];
   const int slot = item / TPB;
-  const int cell0 = (item - slot * TPB) * CELLS + int(threadIdx.x) * W;
+  const int cell0 = (item - slot * TPB) * CELLS + (w % SPLIT) * (CELLS / SPLIT) + int(threadIdx.x) * W;
   const uint32_t fl = a.flags[slot];
   for (int q = threadIdx.x; q < 27; q += blockDim.x) sc.nbr[q] = a.nbr[slot * 27 + q];
   if (threadIdx.x == 0) {
@@ -490,37 +493,77 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, SlotCache& sc, in
     update_any<S, N, false>(a, sc, slot, fl, cell0);
 }
 
-// One workgroup per work tile (PERSIST = false), or a fixed grid of
-// workgroups looping over the tiles (PERSIST = true).
-template <typename S, int N, bool PERSIST>
-__global__ void __launch_bounds__((Geo<S, N>::T)) sweep_kernel(SweepArgs a) {
+// Workgroup splits that keep at least one full wavefront per workgroup.
+template <typename S, int N, int SPLIT>
+constexpr bool split_ok() {
+  return SPLIT == 1 || (Geo<S, N>::T / SPLIT >= 64 && (Geo<S, N>::CELLS / SPLIT) % N == 0);
+}
+
+// One workgroup per work unit (PERSIST = false), or a fixed grid of
+// workgroups looping over the units (PERSIST = true).
+template <typename S, int N, bool PERSIST, int SPLIT>
+__global__ void __launch_bounds__((Geo<S, N>::T / SPLIT)) sweep_kernel(SweepArgs a) {
   __shared__ SlotCache sc;
   if (!PERSIST) {
-    sweep_item<S, N>(a, sc, blockIdx.x);
+    sweep_item<S, N, SPLIT>(a, sc, blockIdx.x);
     return;
   }
-  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) {
-    sweep_item<S, N>(a, sc, w);
+  const int units = a.nwork * SPLIT;
+  for (int w = blockIdx.x; w < units; w += gridDim.x) {
+    sweep_item<S, N, SPLIT>(a, sc, w);
     __syncthreads();
   }
 }
 
-// Launch of one level substep for storage type S.
+// Largest split <= `requested` (1, 2 or 4) valid for storage S and n.
 template <typename S>
-hipError_t launch_sweep_t(int n, const SweepArgs& a, int grid, hipStream_t stream) {
-  auto go = [&](auto nn) -> hipError_t {
+int sweep_split_t(int n, int requested) {
+  auto best = [&](auto nn) -> int {
     constexpr int N = decltype(nn)::value;
-    if (grid < a.nwork)
-      hipLaunchKernelGGL((sweep_kernel<S, N, true>), dim3(grid), dim3(Geo<S, N>::T), 0, stream, a);
-    else
-      hipLaunchKernelGGL((sweep_kernel<S, N, false>), dim3(a.nwork), dim3(Geo<S, N>::T), 0, stream, a);
-    return hipGetLastError();
+    if (requested >= 4 && split_ok<S, N, 4>()) return 4;
+    if (requested >= 2 && split_ok<S, N, 2>()) return 2;
+    return 1;
   };
   switch (n) {
-    case 4: return go(std::integral_constant<int, 4>{});
-    case 8: return go(std::integral_constant<int, 8>{});
-    case 16: return go(std::integral_constant<int, 16>{});
-    case 32: return go(std::integral_constant<int, 32>{});
+    case 4: return best(std::integral_constant<int, 4>{});
+    case 8: return best(std::integral_constant<int, 8>{});
+    case 16: return best(std::integral_constant<int, 16>{});
+    case 32: return best(std::integral_constant<int, 32>{});
+    default: return 1;
+  }
+}
+
+// Launch of one level substep for storage type S: `split` must be the value
+// sweep_split_t returns, grid >= nwork * split launches one workgroup per
+// work unit, a smaller grid a persistent one.
+template <typename S>
+hipError_t launch_sweep_t(int n, const SweepArgs& a, int grid, int split, hipStream_t stream) {
+  auto go = [&](auto nn, auto ss) -> hipError_t {
+    constexpr int N = decltype(nn)::value, SPLIT = decltype(ss)::value;
+    if constexpr (!split_ok<S, N, SPLIT>()) {
+      return hipErrorInvalidValue;
+    } else {
+      constexpr int T = Geo<S, N>::T / SPLIT;
+      if (grid < a.nwork * SPLIT)
+        hipLaunchKernelGGL((sweep_kernel<S, N, true, SPLIT>), dim3(grid), dim3(T), 0, stream, a);
+      else
+        hipLaunchKernelGGL((sweep_kernel<S, N, false, SPLIT>), dim3(a.nwork * SPLIT), dim3(T), 0, stream, a);
+      return hipGetLastError();
+    }
+  };
+  auto by_split = [&](auto nn) -> hipError_t {
+    switch (split) {
+      case 1: return go(nn, std::integral_constant<int, 1>{});
+      case 2: return go(nn, std::integral_constant<int, 2>{});
+      case 4: return go(nn, std::integral_constant<int, 4>{});
+      default: return hipErrorInvalidValue;
+    }
+  };
+  switch (n) {
+    case 4: return by_split(std::integral_constant<int, 4>{});
+    case 8: return by_split(std::integral_constant<int, 8>{});
+    case 16: return by_split(std::integral_constant<int, 16>{});
+    case 32: return by_split(std::integral_constant<int, 32>{});
     default: return hipErrorInvalidValue;
   }
 }

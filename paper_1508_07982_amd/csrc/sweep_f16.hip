@@ -3,8 +3,10 @@
 
 namespace lbm {
 
-hipError_t launch_sweep_f16(int n, const SweepArgs& a, int grid, hipStream_t stream) {
-  return dev::launch_sweep_t<__half>(n, a, grid, stream);
+hipError_t launch_sweep_f16(int n, const SweepArgs& a, int grid, int split, hipStream_t stream) {
+  return dev::launch_sweep_t<__half>(n, a, grid, split, stream);
 }
+
+int sweep_split_f16(int n, int requested) { return dev::sweep_split_t<__half>(n, requested); }
 
 }  // namespace lbm

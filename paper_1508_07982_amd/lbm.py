@@ -9,6 +9,7 @@ library is not built, loading it raises.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -87,8 +88,8 @@ _SIGNATURES = {
     "lbm_mlp_gradient": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p],
     "lbm_mlp_train": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                       ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p],
-    "lbm_set_level_launch": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int],
-    "lbm_get_level_launch": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_set_level_launch": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+    "lbm_get_level_launch": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_autotune": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
     "lbm_block_features": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_plain_targets": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_void_p],
@@ -310,21 +311,44 @@ class Forest:
         _check(self._lib.lbm_block_indicators(self._h, _ptr(feat), _ptr(crit)))
         return feat, crit
 
-    def set_level_launch(self, level, persistent, order=0):
-        _check(self._lib.lbm_set_level_launch(self._h, int(level), int(persistent), int(order)))
+    def set_level_launch(self, level, persistent, order=0, split=1):
+        _check(self._lib.lbm_set_level_launch(self._h, int(level), int(persistent), int(order), int(split)))
 
     def get_level_launch(self, level):
-        p, o = ctypes.c_int(), ctypes.c_int()
-        _check(self._lib.lbm_get_level_launch(self._h, int(level), ctypes.byref(p), ctypes.byref(o)))
-        return p.value, o.value
+        """(persistent, order, split) of the level's sweep launches."""
+        p, o, s = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.lbm_get_level_launch(self._h, int(level), ctypes.byref(p), ctypes.byref(o),
+                                              ctypes.byref(s)))
+        return p.value, o.value, s.value
 
-    def autotune(self, n_steps=2):
+    def autotune(self, n_steps=2, cache=None):
         """Pick each level's launch shape by timing; returns a list of
-        {level, persistent, order, ms_per_level_step}."""
-        res = np.zeros(3 * self.num_levels)
+        {level, persistent, order, split, ms_per_level_step}.  With `cache`
+        (a JSON file path) a shape stored for the same storage form, block
+        size, level and block count is applied without timing, and new
+        results are stored."""
+        key = [f"{self.storage}/n{self.n}/L{L}/b{self.num_blocks(L)}" for L in range(self.num_levels)]
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+        if cache and all(k in table for k in key):
+            out = []
+            for L, k in enumerate(key):
+                e = table[k]
+                self.set_level_launch(L, e["persistent"], e["order"], e["split"])
+                out.append(dict(e, level=L, cached=True))
+            return out
+        res = np.zeros(4 * self.num_levels)
         _check(self._lib.lbm_autotune(self._h, int(n_steps), _ptr(res)))
-        return [{"level": L, "persistent": int(res[3 * L]), "order": int(res[3 * L + 1]),
-                 "ms_per_level_step": float(res[3 * L + 2])} for L in range(self.num_levels)]
+        out = [{"level": L, "persistent": int(res[4 * L]), "order": int(res[4 * L + 1]), "split": int(res[4 * L + 2]),
+                "ms_per_level_step": float(res[4 * L + 3])} for L in range(self.num_levels)]
+        if cache:
+            for L, k in enumerate(key):
+                table[k] = {c: out[L][c] for c in ("persistent", "order", "split", "ms_per_level_step")}
+            with open(cache, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+        return out
 
     def block_features(self):
         """Features (nblocks, 12) from the fused single-pass kernel."""

@@ -1,7 +1,8 @@
 """Launch shapes and the autotuner through the C ABI: per-level persistent
-grids and XCD-grouped tile orders give bitwise the same state as the
-default launch, the autotuner leaves the simulation state exactly where it
-was, and per-level settings survive a regrid."""
+grids, XCD-grouped tile orders and workgroup splits give bitwise the same
+state as the default launch, the autotuner leaves the simulation state
+exactly where it was (and its JSON cache reproduces its choice), and
+per-level settings survive a regrid."""
 
 import numpy as np
 import pytest
@@ -27,19 +28,21 @@ def make(storage="f32", n=8, seed=1):
     return g
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
-@pytest.mark.parametrize("shape", [[(0, 1), (2, 0), (1, 1)], [(4, 1), (0, 1), (8, 0)], [(-1, 1), (-1, 1), (-1, 1)]])
-def test_level_launch_shapes_bitwise_equal(storage, shape):
-    print(f"level launch {storage} {shape}", flush=True)
-    ref = make(storage)
+@pytest.mark.parametrize("storage, n", [("f32", 8), ("f16", 8), ("f64", 8), ("f32", 16), ("f16", 16)])
+@pytest.mark.parametrize("shape", [[(0, 1, 1), (2, 0, 2), (1, 1, 4)], [(4, 1, 2), (0, 1, 4), (8, 0, 1)],
+                                   [(-1, 1, 2), (-1, 1, 1), (-1, 0, 4)]])
+def test_level_launch_shapes_bitwise_equal(storage, n, shape):
+    print(f"level launch {storage} n={n} {shape}", flush=True)
+    ref = make(storage, n)
     ref.set_schedule("direct")
     ref.step_coarse(3)
     want = ref.get_pdfs()
     ref.close()
-    g = make(storage)
-    for L, (p, o) in enumerate(shape):
-        g.set_level_launch(L, p, o)
-        assert g.get_level_launch(L) == (p, o)
+    g = make(storage, n)
+    for L, (p, o, s) in enumerate(shape):
+        g.set_level_launch(L, p, o, s)
+        got = g.get_level_launch(L)
+        assert got[:2] == (p, o) and got[2] in (1, 2, 4) and got[2] <= s
     g.step_coarse(3)
     assert np.array_equal(g.get_pdfs(), want)
     g.close()
@@ -56,10 +59,25 @@ def test_autotune_restores_state_and_applies_choice():
     res = g.autotune(n_steps=1)
     assert len(res) == g.num_levels
     for r in res:
-        assert r["persistent"] in (0, 1, 2, 4, 8) and r["order"] in (0, 1) and r["ms_per_level_step"] > 0
-        assert g.get_level_launch(r["level"]) == (r["persistent"], r["order"])
+        assert r["persistent"] in (0, 1, 2, 4, 8) and r["order"] in (0, 1) and r["split"] in (1, 2, 4)
+        assert r["ms_per_level_step"] > 0
+        assert g.get_level_launch(r["level"]) == (r["persistent"], r["order"], r["split"])
     g.step_coarse(2)
     assert np.array_equal(g.get_pdfs(), want)
+    g.close()
+
+
+def test_autotune_cache_reproduces_choice(tmp_path):
+    cache = str(tmp_path / "launch.json")
+    g = make("f32", seed=7)
+    first = g.autotune(n_steps=1, cache=cache)
+    g.close()
+    g = make("f32", seed=7)
+    again = g.autotune(n_steps=1, cache=cache)
+    assert all(r.get("cached") for r in again)
+    for a, b in zip(first, again):
+        assert (a["persistent"], a["order"], a["split"]) == (b["persistent"], b["order"], b["split"])
+        assert g.get_level_launch(a["level"]) == (a["persistent"], a["order"], a["split"])
     g.close()
 
 
@@ -91,7 +109,7 @@ def test_level_launch_kept_across_regrid():
     a = make("f32", seed=5)
     b = make("f32", seed=5)
     for L in range(b.num_levels):
-        b.set_level_launch(L, 2, 1)
+        b.set_level_launch(L, 2, 1, 2)
     a.step_coarse(1)
     b.step_coarse(1)
     rng = np.random.default_rng(9)
@@ -100,7 +118,7 @@ def test_level_launch_kept_across_regrid():
     a.regrid(flags)
     b.regrid(flags)
     for L in range(min(nl, b.num_levels)):
-        assert b.get_level_launch(L) == (2, 1)
+        assert b.get_level_launch(L)[:2] == (2, 1)
     a.step_coarse(2)
     b.step_coarse(2)
     assert np.array_equal(a.get_pdfs(), b.get_pdfs())
@@ -116,4 +134,6 @@ def test_level_launch_rejects_bad_arguments():
         g.set_level_launch(0, 0, 2)
     with pytest.raises(lbm.LBMError):
         g.set_level_launch(0, 65, 0)
+    with pytest.raises(lbm.LBMError):
+        g.set_level_launch(0, 0, 0, 3)
     g.close()
