@@ -90,6 +90,14 @@ def _db(path):
     return sqlite3.connect(path)
 
 
+def _units_per_tile(name):
+    """Workgroups per work tile of a sweep dispatch: the kernel's last
+    template argument (its split), 1 if absent."""
+    inner = name.split("<", 1)[1].split(">", 1)[0] if "<" in name else ""
+    parts = [p.strip() for p in inner.split(",")]
+    return int(parts[3]) if len(parts) >= 4 and parts[3].isdigit() else 1
+
+
 def _measured_from(db):
     """Dispatch id of the first reduction kernel (the start of the measured
     phase), or 0 if there is none."""
@@ -112,7 +120,7 @@ def trace_summary(results: str, out: str, command: str):
     per_level = {}
     for name, dur, gx, wx, did in rows:
         if "sweep_kernel" in name and did > first:
-            L = level_of_grid.get(gx // max(wx, 1))
+            L = level_of_grid.get(gx // max(wx, 1) // _units_per_tile(name))
             per_level.setdefault((name.rsplit("(", 1)[0], L), []).append(dur)
     with open(out, "w") as fh:
         fh.write(f"# rocprofv3 --kernel-trace --stats summary\n# command: {command}\n")
@@ -122,7 +130,8 @@ def trace_summary(results: str, out: str, command: str):
             fh.write(f"{k[:70]:70s} {len(v):6d} {sum(v) / 1e3:12.1f} {sum(v) / len(v) / 1e3:10.2f} "
                      f"{min(v) / 1e3:10.2f} {max(v) / 1e3:10.2f}\n")
         fh.write(f"\n# measured phase (dispatches after the first reduce_kernel, id {first}): sweep launches by\n"
-                 "# level (level from the grid size = work tiles of that level; None = persistent grid)\n")
+                 "# level (level from the grid size = work tiles of that level times the workgroups per tile;\n"
+                 "# None = persistent grid)\n")
         for (k, L), v in sorted(per_level.items(), key=lambda kv: (kv[0][0], -1 if kv[0][1] is None else kv[0][1])):
             fh.write(f"{k[:60]:60s} level {L}: {len(v):5d} launches, avg {sum(v) / len(v) / 1e3:10.2f} us\n")
     print(open(out).read())
@@ -149,7 +158,7 @@ def traffic_summary(copy_fetch, copy_write, sweep_fetch, sweep_write, out, comma
         return [v for n, v, g, w, d in db.execute(
             "select p.name, p.counter_value, k.grid_x, k.workgroup_x, k.dispatch_id from pmc_events p join kernels k "
             "on p.dispatch_id = k.dispatch_id where p.counter_name = ?", (counter,)) if "sweep_kernel" in n
-            and g // max(w, 1) == tiles[Lf] and d > first]
+            and g // max(w, 1) // _units_per_tile(n) == tiles[Lf] and d > first]
     fin_f = finest(sweep_fetch, "FETCH_SIZE")
     fin_w = finest(sweep_write, "WRITE_SIZE")
     if not fin_f or not fin_w:
