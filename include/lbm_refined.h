@@ -165,9 +165,10 @@ int lbm_set_launch(lbm_forest *f, int persistent);
 
 /* Launch shape of one level's sweep: persistent as in lbm_set_launch (-1:
  * follow the forest-wide setting); order 0 sweeps the work tiles in
- * canonical order, order 1 groups them so that each of the 8 XCDs (to which
- * workgroups are dispatched round-robin) sweeps one contiguous range of
- * tiles; split (1, 2 or 4) sweeps each work tile with that many workgroups
+ * canonical order, order 1 maps workgroups to work units so that each of
+ * the 8 XCDs (to which workgroups are dispatched round-robin) sweeps one
+ * contiguous range of them; split (1, 2 or 4) sweeps each work tile with
+ * that many workgroups
  * of 256 / split lanes (the largest allowed split <= the request is used:
  * a workgroup keeps at least one full wavefront).  Synchronizes the stream;
  * invalidates captured graphs; kept across lbm_regrid for levels that still

@@ -195,8 +195,9 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   a.par = parent_cur;
   a.fine0 = fine0;
   a.fine1 = fine1;
-  a.work = d.order == 1 && d.work_xcd ? d.work_xcd : d.work;
+  a.work = d.work;
   a.nwork = d.nwork;
+  a.xcd = d.order;
   a.substep = substep;
   a.collide = 1;
   a.nbr = d.nbr;
@@ -240,29 +241,6 @@ int grid_for(const lbm_forest* f, int level, int nwork) {
 hipError_t launch_level(const lbm_forest* f, const Op& op) {
   return launch_sweep(f->storage, f->n, op.args, grid_for(f, op.level, op.args.nwork), f->lv[op.level].split,
                       f->stream);
-}
-
-// Tile order 1: workgroups are dispatched round-robin over the 8 XCDs
-// (workgroup w to XCD w % 8, also for a persistent grid, whose size is a
-// multiple of 8), so entry w of the list takes canonical tile
-// start[w % 8] + w / 8 and each XCD sweeps one contiguous range of tiles,
-// keeping the halo planes that neighbouring tiles share in its own L2.
-constexpr int kXcds = 8;
-
-std::vector<int32_t> xcd_grouped(const std::vector<int32_t>& canon) {
-  const int64_t n = int64_t(canon.size());
-  std::vector<int64_t> start(kXcds + 1, 0);
-  for (int x = 0; x < kXcds; ++x) start[x + 1] = start[x] + (n - x + kXcds - 1) / kXcds;
-  std::vector<int32_t> out(canon.size());
-  for (int64_t w = 0; w < n; ++w) out[w] = canon[start[w % kXcds] + w / kXcds];
-  return out;
-}
-
-// Apply level L's tile order (uploads the grouped list when first needed).
-int apply_order(lbm_forest* f, int L) {
-  LevelDev& v = f->lv[L];
-  if (v.order != 1 || v.work_xcd || v.nwork == 0) return LBM_OK;
-  return upload(v.allocs, &v.work_xcd, xcd_grouped(f->tabs[L].work));
 }
 
 int run_ops(lbm_forest* f, const std::vector<Op>& ops, bool per_block) {
@@ -596,8 +574,6 @@ int lbm_set_level_launch(lbm_forest* f, int level, int persistent, int order, in
   f->lv[level].persistent = persistent;
   f->lv[level].order = order;
   f->lv[level].split = sweep_split(f->storage, f->n, split);
-  int rc = apply_order(f, level);
-  if (rc) return rc;
   invalidate_graphs(f);
   return LBM_OK;
 }
@@ -652,7 +628,6 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
         f->lv[L].persistent = kCand[c][0];
         f->lv[L].order = kCand[c][1];
         f->lv[L].split = sweep_split(f->storage, f->n, kCand[c][2]);
-        if ((rc = apply_order(f, L))) return rc;
       }
       if ((rc = lbm_time_sweeps(f, 1, ms.data(), cnt.data()))) return rc;  // warm-up
       if ((rc = lbm_time_sweeps(f, n_steps, ms.data(), cnt.data()))) return rc;
@@ -671,7 +646,6 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
       f->lv[L].persistent = bp[L];
       f->lv[L].order = bo[L];
       f->lv[L].split = bs[L];
-      if ((rc = apply_order(f, L))) return rc;
       result[4 * L] = bp[L];
       result[4 * L + 1] = bo[L];
       result[4 * L + 2] = bs[L];
@@ -959,8 +933,6 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
     f->rot_prev = f->rot;
     f->steps_since_state = 0;
     set_level_omegas(f);
-    for (int L = 0; L < int(f->lv.size()); ++L)
-      if ((rc2 = apply_order(f, L))) return rc2;
     return LBM_OK;
   };
   rc = body();

@@ -20,6 +20,7 @@ struct SweepArgs {
   const void* fine1;          // level-(L+1) state after the first of its two substeps
   const int32_t* work;        // work tiles: slot * tiles_per_block + tile
   int32_t nwork;
+  int32_t xcd;                // 1: work units grouped by XCD (see xcd_unit in the sweep)
   int32_t substep;            // 1 or 2
   int32_t collide;            // 1: collide interior cells (normal); 0: write the streamed values
   const int32_t* nbr;         // [slot][27]

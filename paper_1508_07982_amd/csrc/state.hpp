@@ -31,9 +31,8 @@ struct LevelDev {
   int32_t nchunks = 0;
   void* coal = nullptr;         // coalesced values [fine row][19][n^3]
   int32_t* work = nullptr;      // work tiles in canonical order
-  int32_t* work_xcd = nullptr;  // the same tiles in XCD-grouped order (order 1), allocated on demand
   int persistent = -1;          // launch shape of this level; -1: the forest-wide setting
-  int order = 0;                // 0 canonical tile order, 1 XCD-grouped
+  int order = 0;                // 0 canonical unit order, 1 XCD-grouped (SweepArgs::xcd)
   int split = 1;                // workgroups per work tile (1, 2 or 4; see sweep_split)
   double omega = 0.0;
   std::vector<void*> allocs;  // device memory owned by this level

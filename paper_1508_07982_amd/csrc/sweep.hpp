@@ -499,18 +499,29 @@ constexpr bool split_ok() {
   return SPLIT == 1 || (Geo<S, N>::T / SPLIT >= 64 && (Geo<S, N>::CELLS / SPLIT) % N == 0);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b to
+// XCD b % 8), each XCD with its own L2.  xcd_unit maps workgroup b to a work
+// unit such that every XCD sweeps one contiguous range of units: the halo
+// rows that neighbouring tiles (and the parts of one tile) share then meet
+// in the same L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_unit(int b, int n) {
+  const int x = b & 7, r = b >> 3, q = n >> 3, rem = n & 7;
+  return x * q + (x < rem ? x : rem) + r;
+}
+
 // One workgroup per work unit (PERSIST = false), or a fixed grid of
 // workgroups looping over the units (PERSIST = true).
 template <typename S, int N, bool PERSIST, int SPLIT>
 __global__ void __launch_bounds__((Geo<S, N>::T / SPLIT)) sweep_kernel(SweepArgs a) {
   __shared__ SlotCache sc;
+  const int units = a.nwork * SPLIT;
   if (!PERSIST) {
-    sweep_item<S, N, SPLIT>(a, sc, blockIdx.x);
+    const int b = int(blockIdx.x);
+    sweep_item<S, N, SPLIT>(a, sc, a.xcd ? xcd_unit(b, units) : b);
     return;
   }
-  const int units = a.nwork * SPLIT;
   for (int w = blockIdx.x; w < units; w += gridDim.x) {
-    sweep_item<S, N, SPLIT>(a, sc, w);
+    sweep_item<S, N, SPLIT>(a, sc, a.xcd ? xcd_unit(w, units) : w);
     __syncthreads();
   }
 }
