@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: the refined grid lives in one GPU's HBM and this build has no "
+        print(f"bench.py measures one GPU: the refined grid lives in one GPU's HBM and the library has no "
               f"multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 

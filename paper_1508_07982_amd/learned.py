@@ -19,7 +19,7 @@ the initial blob cores reach the finest level.
 
     python -m paper_1508_07982_amd.learned [--n 16] [--max-level 4] [--steps 500]
         [--every 50] [--train-seeds 11 12] [--test-seed 5] [--snapshots 20000]
-        [--out gpurun_out/learned_report.json]
+        [--out learned_report.json]
 """
 
 from __future__ import annotations
