@@ -137,6 +137,32 @@ int make_levels(int n, size_t s, const std::vector<LevelTables>& tabs, std::vect
       uint8_t* p = nullptr;
       if ((rc = dev_alloc(v.allocs, &p, size_t(t.fine_blocks) * 19 * n3 * s))) return rc;
       v.coal = p;
+      if ((rc = dev_alloc(v.allocs, &p, size_t(t.fine_blocks) * 10 * n * n * s))) return rc;
+      v.coal_x = p;
+    }
+    // face rows: the level-L blocks that level L-1's coalescence reads
+    if (L > 0) {
+      std::vector<int32_t> fidx(size_t(t.nblocks), -1), fslot;
+      for (int32_t b : tabs[L - 1].fine_nbr) {
+        if (b < 0) continue;
+        if (b >= t.nblocks) return fail(LBM_E_STATE, "level %zu: fine neighbour %d out of range", L - 1, b);
+        if (fidx[size_t(b)] < 0) {
+          fidx[size_t(b)] = int32_t(fslot.size());
+          fslot.push_back(b);
+        }
+      }
+      v.nface = int32_t(fslot.size());
+      if (v.nface) {
+        if ((rc = upload(v.allocs, &v.face_index, fidx))) return rc;
+        if ((rc = upload(v.allocs, &v.face_slot, fslot))) return rc;
+        const size_t fbytes = size_t(v.nface) * 10 * n * n * s;
+        for (int b = 0; b < v.nbuf; ++b) {
+          uint8_t* p = nullptr;
+          if ((rc = dev_alloc(v.allocs, &p, fbytes))) return rc;
+          HIP_TRY(hipMemset(p, 0, fbytes));
+          v.xface[b] = p;
+        }
+      }
     }
     if ((rc = upload(v.allocs, &v.work, t.work))) return rc;
   }
@@ -150,6 +176,18 @@ void free_levels(std::vector<LevelDev>& lv) {
 }
 
 void set_level_omegas(lbm_forest* f);
+
+// x-face copies of every level's current buffer, after the state was
+// written by anything but a sweep (see CoalArgs).
+int refresh_faces(lbm_forest* f) {
+  for (size_t L = 0; L < f->lv.size(); ++L) {
+    const LevelDev& v = f->lv[L];
+    if (v.nface == 0) continue;
+    const int b = f->rot[L];
+    HIP_TRY(launch_face_copy(f->storage, f->n, v.buf[b], v.xface[b], v.face_slot, v.nface, f->stream));
+  }
+  return LBM_OK;
+}
 
 void invalidate_graphs(lbm_forest* f) {
   for (auto& g : f->graphs) (void)hipGraphExecDestroy(g.second);
@@ -165,26 +203,32 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   const int nlev = int(f->lv.size());
   const void* cur;
   const void* prev = nullptr;
-  void* nxt;
+  int nb;  // buffer written
   if (L == 0) {
     cur = d.buf[r[0]];
-    nxt = d.buf[r[0] ^ 1];
+    nb = r[0] ^ 1;
   } else if (substep == 1) {
     cur = d.buf[r[L]];
-    nxt = d.buf[(r[L] + 1) % 3];
+    nb = (r[L] + 1) % 3;
   } else {
     prev = d.buf[r[L]];
     cur = d.buf[(r[L] + 1) % 3];
-    nxt = d.buf[(r[L] + 2) % 3];
+    nb = (r[L] + 2) % 3;
   }
+  void* nxt = d.buf[nb];
   const void* fine0 = nullptr;
   const void* fine1 = nullptr;
+  const void* fine0_x = nullptr;
+  const void* fine1_x = nullptr;
   if (L + 1 < nlev) {
     const int rf = r[L + 1];
     emit(f, L + 1, 1, r, cur, ops);
     emit(f, L + 1, 2, r, cur, ops);
-    fine0 = f->lv[L + 1].buf[rf];
-    fine1 = f->lv[L + 1].buf[(rf + 1) % 3];
+    const LevelDev& fd = f->lv[L + 1];
+    fine0 = fd.buf[rf];
+    fine1 = fd.buf[(rf + 1) % 3];
+    fine0_x = fd.xface[rf];
+    fine1_x = fd.xface[(rf + 1) % 3];
   }
   Op op;
   op.level = L;
@@ -204,6 +248,9 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   a.flags = d.flags;
   a.fine_index = d.fine_index;
   a.coal = d.coal;
+  a.coal_x = d.coal_x;
+  a.face_out = d.xface[nb];
+  a.face_index = d.face_index;
   a.omega = float(d.omega);
   a.omega64 = d.omega;
   a.err = f->d_err;
@@ -216,6 +263,10 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
     c.coal.fine0 = fine0;
     c.coal.fine1 = fine1;
     c.coal.out = d.coal;
+    c.coal.out_x = d.coal_x;
+    c.coal.fine0_x = fine0_x;
+    c.coal.fine1_x = fine1_x;
+    c.coal.fine_face = f->lv[L + 1].face_index;
     c.coal.pairs = d.pairs;
     c.coal.chunks = d.chunks;
     c.coal.nchunks = d.nchunks;
@@ -538,6 +589,8 @@ int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
       HIP_TRY(launch_init(f->storage, f->n, v.buf[0], d_rho + off, d_u + 3 * off, v.ncells, f->stream));
       off += v.ncells;
     }
+    int rc2 = refresh_faces(f);
+    if (rc2) return rc2;
     HIP_TRY(hipStreamSynchronize(f->stream));
     return LBM_OK;
   };
@@ -665,6 +718,11 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
   f->rot_prev = rot_prev;
   f->steps_since_state = since;
   invalidate_graphs(f);
+  if (!rc) rc = refresh_faces(f);  // the restored buffers' x-face copies
+  if (!rc) {
+    const hipError_t e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) rc = fail(LBM_E_HIP, "autotune: %s", hipGetErrorString(e));
+  }
   cleanup();
   return rc;
 }
@@ -835,6 +893,7 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
       if ((rc2 = upload(scratch, &dwork, work))) return rc2;
       SweepArgs a = last->args;
       a.nxt = tmp;
+      a.face_out = nullptr;
       a.collide = 0;
       a.work = dwork;
       a.nwork = int32_t(work.size());
@@ -933,7 +992,7 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
     f->rot_prev = f->rot;
     f->steps_since_state = 0;
     set_level_omegas(f);
-    return LBM_OK;
+    return refresh_faces(f);
   };
   rc = body();
   cleanup();
@@ -1010,6 +1069,9 @@ int lbm_set_pdfs(lbm_forest* f, const double* h) {
       HIP_TRY(hipMemcpyAsync(d, h + 19 * off, v.ncells * 19 * sizeof(double), hipMemcpyHostToDevice, f->stream));
       HIP_TRY(launch_set_pdfs(f->storage, f->n, current_buffer_mut(f, int(L)), d, v.ncells, f->stream));
       f->steps_since_state = 0;
+      if (v.nface)
+        HIP_TRY(launch_face_copy(f->storage, f->n, current_buffer(f, int(L)), v.xface[f->rot[L]], v.face_slot,
+                                 v.nface, f->stream));
       HIP_TRY(hipStreamSynchronize(f->stream));
       return LBM_OK;
     };

@@ -211,6 +211,9 @@ __global__ void __launch_bounds__(kCoalThreads) coalesce_kernel(CoalArgs c) {
     const int oct = (i >= H ? 1 : 0) | (j >= H ? 2 : 0) | (k >= H ? 4 : 0);
     const int32_t* fn = fns + oct * 27;
     const int cx = 2 * (i & (H - 1)), cy = 2 * (j & (H - 1)), cz = 2 * (k & (H - 1));
+    // a fine value at the x face it leaves through comes from the x-face copy
+    const int xout = EX < 0 ? 0 : N - 1;
+    const bool xcopy = EX != 0 && c.fine1_x != nullptr;
     C v[8];
     bool fine[8];
 #pragma unroll
@@ -219,13 +222,18 @@ __global__ void __launch_bounds__(kCoalThreads) coalesce_kernel(CoalArgs c) {
       const int fy = fn[13 + nb_side<N>(yx) + 3 * nb_side<N>(yy) + 9 * nb_side<N>(yz)];
       const int zx = yx - EX, zy = yy - EY, zz = yz - EZ;
       const int fz = fn[13 + nb_side<N>(zx) + 3 * nb_side<N>(zy) + 9 * nb_side<N>(zz)];
-      const S* p = fy >= 0 ? static_cast<const S*>(c.fine1) +
-                                 pdf_index<N>(A, uint32_t(fy), uint32_t((yx & (N - 1)) + N * ((yy & (N - 1)) +
-                                                                                              N * (yz & (N - 1)))))
-                   : fz >= 0 ? static_cast<const S*>(c.fine0) +
-                                   pdf_index<N>(A, uint32_t(fz), uint32_t((zx & (N - 1)) + N * ((zy & (N - 1)) +
-                                                                                                N * (zz & (N - 1)))))
-                             : static_cast<const S*>(c.cur);
+      const S* p = static_cast<const S*>(c.cur);
+      if (fy >= 0) {
+        const int lx = yx & (N - 1), jk = (yy & (N - 1)) + N * (yz & (N - 1));
+        const int fr = xcopy && lx == xout ? c.fine_face[fy] : -1;
+        p = fr >= 0 ? static_cast<const S*>(c.fine1_x) + xface_index_rt<N>(A, uint32_t(fr), uint32_t(jk))
+                    : static_cast<const S*>(c.fine1) + pdf_index<N>(A, uint32_t(fy), uint32_t(lx + N * jk));
+      } else if (fz >= 0) {
+        const int lx = zx & (N - 1), jk = (zy & (N - 1)) + N * (zz & (N - 1));
+        const int fr = xcopy && lx == xout ? c.fine_face[fz] : -1;
+        p = fr >= 0 ? static_cast<const S*>(c.fine0_x) + xface_index_rt<N>(A, uint32_t(fr), uint32_t(jk))
+                    : static_cast<const S*>(c.fine0) + pdf_index<N>(A, uint32_t(fz), uint32_t(lx + N * jk));
+      }
       fine[q] = fy >= 0 || fz >= 0;
       v[q] = Form<S>::ld(p);
     }
@@ -233,8 +241,24 @@ __global__ void __launch_bounds__(kCoalThreads) coalesce_kernel(CoalArgs c) {
     C sum = C(0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) sum += fine[q] ? v[q] : regular;
-    Form<S>::st(static_cast<S*>(c.out) + pdf_index<N>(A, uint32_t(row), uint32_t(cell)), sum * C(0.125));
+    // a pair entering through an x face goes to the x-face layout
+    S* o = EX != 0 && i == (EX > 0 ? 0 : N - 1)
+               ? static_cast<S*>(c.out_x) + xface_index_rt<N>(A, uint32_t(row), uint32_t(j + N * k))
+               : static_cast<S*>(c.out) + pdf_index<N>(A, uint32_t(row), uint32_t(cell));
+    Form<S>::st(o, sum * C(0.125));
   }
+}
+
+// x-face copy of a buffer (see CoalArgs): one thread per element of xf.
+template <typename S, int N>
+__global__ void face_copy_kernel(const S* buf, S* xf, const int32_t* face_slot, int64_t count) {
+  constexpr int N2 = N * N;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const int64_t row = e / (kXDirs * N2);
+  const int A = xdir_dir(int((e / N2) % kXDirs));
+  const int jk = int(e % N2);
+  xf[e] = buf[pdf_index<N>(A, uint32_t(face_slot[row]), uint32_t((ex(A) < 0 ? 0 : N - 1) + N * jk))];
 }
 
 template <typename F>
@@ -350,6 +374,19 @@ hipError_t launch_coalesce(int storage, int n, const CoalArgs& a, hipStream_t st
     using S = decltype(s);
     constexpr int N = decltype(nn)::value;
     hipLaunchKernelGGL((coalesce_kernel<S, N>), dim3(a.nchunks), dim3(kCoalThreads), 0, stream, a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_face_copy(int storage, int n, const void* buf, void* xf, const int32_t* face_slot, int32_t nrows,
+                            hipStream_t stream) {
+  if (nrows <= 0) return hipSuccess;
+  return dispatch(storage, n, [&](auto s, auto nn) {
+    using S = decltype(s);
+    constexpr int N = decltype(nn)::value;
+    const int64_t count = int64_t(nrows) * kXDirs * N * N;
+    hipLaunchKernelGGL((face_copy_kernel<S, N>), dim3(grid_for(count, 256)), dim3(256), 0, stream,
+                       static_cast<const S*>(buf), static_cast<S*>(xf), face_slot, count);
     return hipGetLastError();
   });
 }

@@ -27,6 +27,9 @@ struct SweepArgs {
   const uint32_t* flags;      // [slot]
   const int32_t* fine_index;  // [slot]
   const void* coal;           // coalesced values of this substep, [row][19][n^3] (see CoalArgs)
+  const void* coal_x;         // the same for the pairs that cross an x face, [row][10][n^2]
+  void* face_out;             // x-face copy of nxt, [face row][10][n^2] (null: not kept)
+  const int32_t* face_index;  // [slot]: face row, -1 for a slot without one
   float omega;                // omega_L (FP32 arithmetic forms)
   double omega64;             // omega_L (FP64 form)
   int* err;                   // error bits (table lookup failures)
@@ -39,12 +42,24 @@ enum ErrBits : int { kErrNoSource = 1, kErrNoChild = 2 };
 // coalesced pair (X, a) of a slot with finer neighbours, the mean over the 8
 // children of X of what the finer level's second stream pulled into them,
 // written to out[row][a][cell] (block-major like the state, one block per
-// fine_nbr row).
+// fine_nbr row), or to out_x for a pair that enters through an x face
+// (cell x = 0 with e_a,x = +1, x = n - 1 with e_a,x = -1; x-face layout).
+//
+// Every level L >= 1 block that a coarser block's fine_nbr lists has a face
+// row: each sweep of level L also writes the values leaving the block
+// through its x faces (cell x = 0 for e_a,x = -1, x = n - 1 for +1) into the
+// x-face copy of the buffer it writes, and the coalescence reads those from
+// the copy (one element per line otherwise).  A buffer written by anything
+// but a sweep has its copy refreshed by launch_face_copy.
 struct CoalArgs {
   const void* cur;            // level-L state read by the following sweep (the regular sources)
   const void* fine0;          // level-(L+1) state at the start of the parent step
   const void* fine1;          // level-(L+1) state after its first substep
   void* out;                  // [row][19][n^3]
+  void* out_x;                // [row][10][n^2]
+  const void* fine0_x;        // x-face copies of fine0 and fine1 (null: none kept)
+  const void* fine1_x;
+  const int32_t* fine_face;   // level-(L+1) [slot]: face row or -1
   const uint32_t* pairs;      // [pair]: (direction << 16) | cell, grouped by row
   const int32_t* chunks;      // [chunk][3]: row, first pair, end pair
   int32_t nchunks;
@@ -54,6 +69,11 @@ struct CoalArgs {
 };
 
 hipError_t launch_coalesce(int storage, int n, const CoalArgs& a, hipStream_t stream);
+
+// x-face copy of a whole buffer: xf[row] takes the x-face values of block
+// face_slot[row], for rows [0, nrows).
+hipError_t launch_face_copy(int storage, int n, const void* buf, void* xf, const int32_t* face_slot, int32_t nrows,
+                            hipStream_t stream);
 
 // Cells per work tile of the sweep kernel (one workgroup's share).
 int sweep_tile_cells(int storage, int n);

@@ -13,17 +13,17 @@ namespace lbm {
 namespace dev {
 
 // ---- D3Q19 velocity set (rest, 6 faces, 12 edges; opposites adjacent) ----
-__host__ __device__ constexpr int ex(int a) {
+__host__ __device__ __forceinline__ constexpr int ex(int a) {
   return a == 1 || a == 7 || a == 9 || a == 11 || a == 13 ? 1 : (a == 2 || a == 8 || a == 10 || a == 12 || a == 14 ? -1 : 0);
 }
-__host__ __device__ constexpr int ey(int a) {
+__host__ __device__ __forceinline__ constexpr int ey(int a) {
   return a == 3 || a == 7 || a == 10 || a == 15 || a == 17 ? 1 : (a == 4 || a == 8 || a == 9 || a == 16 || a == 18 ? -1 : 0);
 }
-__host__ __device__ constexpr int ez(int a) {
+__host__ __device__ __forceinline__ constexpr int ez(int a) {
   return a == 5 || a == 11 || a == 14 || a == 15 || a == 18 ? 1 : (a == 6 || a == 12 || a == 13 || a == 16 || a == 17 ? -1 : 0);
 }
 template <typename C>
-__host__ __device__ constexpr C wgt(int a) {
+__host__ __device__ __forceinline__ constexpr C wgt(int a) {
   return a == 0 ? C(1) / C(3) : (a <= 6 ? C(1) / C(18) : C(1) / C(36));
 }
 
@@ -48,6 +48,53 @@ __host__ __device__ constexpr uint64_t pdf_at(int a, uint64_t idx) {
 __host__ __device__ inline uint64_t pdf_at_rt(int a, uint64_t idx, uint64_t n3) {
   return (idx / n3 * kQ + uint64_t(a)) * n3 + idx % n3;
 }
+
+// ---- x faces ----------------------------------------------------------------
+// Values that cross a block's x faces (cells x = 0 or n - 1 of one direction)
+// are n apart in the block-major layout, one element per 128-byte line.
+// Where a kernel reads or writes many of them, they are kept in an x-face
+// buffer instead: one element per (row, x direction, y, z), the 10
+// directions with a nonzero x component numbered in direction order,
+// element (row, xdir_index(a), j + n k) at (10 row + xdir_index(a)) n^2 +
+// j + n k.
+constexpr int kXDirs = 10;
+__host__ __device__ __forceinline__ constexpr int xdir_index(int a) {
+  int q = 0;
+  for (int b = 0; b < a; ++b) q += ex(b) != 0 ? 1 : 0;
+  return q;
+}
+// the direction with x-direction number q
+__host__ __device__ __forceinline__ constexpr int xdir_dir(int q) {
+  int a = 0;
+  for (int seen = -1; a < 19; ++a) {
+    seen += ex(a) != 0 ? 1 : 0;
+    if (ex(a) != 0 && seen == q) break;
+  }
+  return a;
+}
+// element (row, xdir_index(A), jk), A known at compile time
+template <int N, int A>
+__device__ __forceinline__ uint64_t xface_index(uint64_t row, uint32_t jk) {
+  constexpr uint64_t off = uint64_t(xdir_index(A)) * uint64_t(N * N);
+  return row * uint64_t(kXDirs * N * N) + off + jk;
+}
+// the same for a direction known only at run time
+__host__ __device__ __forceinline__ constexpr int xdir_index_rt(int a) {
+  // directions 1, 2 and 7 .. 14 have a nonzero x component
+  return a <= 2 ? a - 1 : a - 5;
+}
+template <int N>
+__device__ __forceinline__ uint64_t xface_index_rt(int a, uint64_t row, uint32_t jk) {
+  return (row * kXDirs + uint64_t(xdir_index_rt(a))) * uint64_t(N * N) + jk;
+}
+static_assert(xdir_index(1) == 0 && xdir_index(2) == 1 && xdir_index(7) == 2 && xdir_index(14) == 9, "x directions");
+constexpr bool xdir_rt_matches() {
+  for (int a = 0; a < 19; ++a)
+    if (ex(a) != 0 && xdir_index_rt(a) != xdir_index(a)) return false;
+  return true;
+}
+static_assert(xdir_rt_matches(), "x directions");
+static_assert(xdir_dir(0) == 1 && xdir_dir(1) == 2 && xdir_dir(2) == 7 && xdir_dir(9) == 14, "x directions");
 
 // ---- storage forms --------------------------------------------------------
 template <typename S>

@@ -39,11 +39,13 @@
 namespace lbm {
 namespace dev {
 
-// Per-workgroup copy of the slot's neighbour table and, for a slot with
-// finer neighbours, its row in the coalesced-value buffer.
+// Per-workgroup copy of the slot's neighbour table, for a slot with finer
+// neighbours its row in the coalesced-value buffers, and its face row (-1:
+// no x-face copy written).
 struct SlotCache {
   int32_t nbr[27];
   int32_t fine_row;
+  int32_t face_row;
 };
 
 // Neighbour offset (-1, 0, +1) of a local coordinate after a shift.
@@ -99,19 +101,17 @@ __device__ __forceinline__ const S* coarse_source(const SweepArgs& a, const Slot
 
 // Coalescence (eq. ftoc): the value of a coalesced pair comes from the
 // coalescence launch that precedes this sweep (see CoalArgs), stored like
-// the state at the slot's fine row.
+// the state at the slot's fine row, or in the x-face layout for a pair that
+// enters through an x face.
 template <typename S, int N, int A>
 __device__ __forceinline__ const S* coalesced_source(const SweepArgs& a, const SlotCache& sc, int i, int j, int k) {
+  constexpr int EX = ex(A);
+  if constexpr (EX != 0) {
+    if (i == (EX == 1 ? 0 : N - 1))
+      return static_cast<const S*>(a.coal_x) + xface_index<N, A>(uint32_t(sc.fine_row), uint32_t(j + N * k));
+  }
   return static_cast<const S*>(a.coal) + pdf_index<N>(A, uint32_t(sc.fine_row), uint32_t(i + N * (j + N * k)));
 }
-
-// Index of direction A among the 10 directions with a nonzero x component.
-constexpr int xdir_index(int A) {
-  int q = 0;
-  for (int b = 0; b < A; ++b) q += ex(b) != 0 ? 1 : 0;
-  return q;
-}
-constexpr int kXDirs = 10;
 
 // Ordinary pull of direction A for the W cells (i0 .. i0+W-1, j, k) of one
 // lane, in two phases so that every load of the lane is in flight before
@@ -308,6 +308,24 @@ __device__ __forceinline__ void collide(C (*h)[W], int c, C om) {
   relax_pairs<C, W>(h, c, base, ux, uy, uz, omc, om * wgt<C>(1), om * wgt<C>(7));
 }
 
+// x-face copy of the lane's output (see CoalArgs): the lanes at the two ends
+// of a row also write the values of their end cell that leave the block
+// through the x face there (directions with e_x = SIDE).
+template <typename S, int N, int SIDE, int A = 1>
+__device__ __forceinline__ void store_face_side(S* __restrict__ f, uint64_t row, uint32_t jk,
+                                                typename Form<S>::C (*h)[Geo<S, N>::W]) {
+  if constexpr (ex(A) == SIDE) Form<S>::st(f + xface_index<N, A>(row, jk), h[A][SIDE < 0 ? 0 : Geo<S, N>::W - 1]);
+  if constexpr (A + 1 < 19) store_face_side<S, N, SIDE, A + 1>(f, row, jk, h);
+}
+template <typename S, int N>
+__device__ __forceinline__ void store_faces(const SweepArgs& a, int row, int i0, int j, int k,
+                                            typename Form<S>::C (*h)[Geo<S, N>::W]) {
+  S* __restrict__ f = static_cast<S*>(a.face_out);
+  const uint32_t jk = uint32_t(j + N * k);
+  if (i0 == 0) store_face_side<S, N, -1>(f, uint64_t(row), jk, h);
+  if (i0 == N - Geo<S, N>::W) store_face_side<S, N, 1>(f, uint64_t(row), jk, h);
+}
+
 template <typename S, int N, bool SIMPLE>
 __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl, int cell0) {
   using C = typename Form<S>::C;
@@ -325,6 +343,7 @@ __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache&
   S* __restrict__ nxt = static_cast<S*>(a.nxt) + pdf_index<N>(0, uint32_t(slot), uint32_t(cell0));
 #pragma unroll
   for (int d = 0; d < 19; ++d) Vec<S>::store(nxt + d * N3, h[d]);
+  if (sc.face_row >= 0) store_faces<S, N>(a, sc.face_row, i0, j, k, h);
 }
 
 // ---- packed FP16 path: 8 cells per lane as 4 registers of half pairs ------
@@ -430,6 +449,16 @@ __device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& s
   if constexpr (A + 1 < 19) fixups_h8<N, A + 1>(a, sc, m, fl, i0, j, k, q);
 }
 
+// store_face_side for the packed lane: cell 0 is the low half of register
+// 0, cell 7 the high half of register 3
+template <int N, int SIDE, int A = 1>
+__device__ __forceinline__ void store_face_side_h8(uint16_t* __restrict__ f, uint64_t row, uint32_t jk,
+                                                   const uint32_t (*q)[4]) {
+  if constexpr (ex(A) == SIDE)
+    f[xface_index<N, A>(row, jk)] = uint16_t(SIDE < 0 ? (q[A][0] & 0xFFFFu) : (q[A][3] >> 16));
+  if constexpr (A + 1 < 19) store_face_side_h8<N, SIDE, A + 1>(f, row, jk, q);
+}
+
 template <int N, bool SIMPLE>
 __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl,
                                                int cell0) {
@@ -460,6 +489,12 @@ __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCac
     const u32x4 t = {q[d][0], q[d][1], q[d][2], q[d][3]};
     __builtin_nontemporal_store(t, reinterpret_cast<u32x4*>(nxt + d * N3));
   }
+  if (sc.face_row >= 0) {  // x-face copy (see store_faces)
+    uint16_t* __restrict__ f = static_cast<uint16_t*>(a.face_out);
+    const uint32_t jk = uint32_t(j + N * k);
+    if (i0 == 0) store_face_side_h8<N, -1>(f, uint64_t(sc.face_row), jk, q);
+    if (i0 == N - 8) store_face_side_h8<N, 1>(f, uint64_t(sc.face_row), jk, q);
+  }
 }
 
 template <typename S, int N, bool SIMPLE>
@@ -485,6 +520,7 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, SlotCache& sc, in
     const int row = fl & kHasFine ? a.fine_index[slot] : 0;
     if (row < 0) atomicOr(a.err, kErrNoChild);
     sc.fine_row = row < 0 ? 0 : row;
+    sc.face_row = a.face_out ? a.face_index[slot] : -1;
   }
   __syncthreads();
   if (fl & kAllSameLevel)

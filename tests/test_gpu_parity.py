@@ -204,6 +204,39 @@ def test_raw_pdf_roundtrip_and_packet_trace():
         assert abs(out[i, a] - 1.0) < 1e-15
 
 
+@pytest.mark.parametrize("storage, n, tol", [("f64", 8, 1e-15), ("f32", 4, 1e-7), ("f16", 8, 1e-4)])
+def test_set_pdfs_then_streaming_matches_oracle(storage, n, tol):
+    """omega = 0 (streaming, explosion and coalescence only) from random PDFs
+    written with set_pdfs over an already stepped state: every value the
+    coalescence reads, the x-face values of the fine blocks included, must
+    come from the state that was set."""
+    R, n, Lmax, refine = forest_three(n)
+    say(f"set_pdfs + streaming {storage} n={n}")
+    of = Forest.build(R, n, Lmax, refine)
+    o = RefinedOracle(of, 0.0)
+    g = lbm.Forest(R, n, Lmax, refine=refine, storage=storage)
+    g.set_level_omega(0.0)
+    N = g.num_cells()
+    _, w = lbm.lattice()
+    g.init_pdfs(np.ones(N), np.zeros((N, 3)))
+    g.step_coarse(1)
+    rng = np.random.default_rng(7)
+    f = w[None, :] * (1.0 + 0.1 * rng.uniform(-1, 1, (N, 19)))
+    g.set_pdfs(f - w[None, :])
+    f = g.get_pdfs() + w[None, :]  # as stored (rounded to the storage form)
+    off = 0
+    for L in range(o.num_levels):
+        m = o.n_int(L)
+        o.set_interior_pdfs(L, f[off:off + m])
+        off += m
+    o.step(2)
+    g.step_coarse(2)
+    got = g.get_pdfs() + w[None, :]
+    want = np.concatenate([o.interior_pdfs(L) for L in range(o.num_levels)])
+    assert np.max(np.abs(got - want)) < tol
+    g.close()
+
+
 def test_nonfinite_detected():
     R, n, Lmax, refine = forest_two(4)
     say("nonfinite")
