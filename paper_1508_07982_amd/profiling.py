@@ -187,6 +187,29 @@ def traffic_summary(copy_fetch, copy_write, sweep_fetch, sweep_write, out, comma
         fh.write(f"algorithmic_bytes_per_launch: {alg}\n")
         fh.write(f"traffic_over_algorithmic: {(fetch + write) / alg:.4f}\n")
         fh.write(f"launches_averaged: {len(fin_f)}\n")
+        # the coalescence launches, one group per level (grid = that level's
+        # pair chunks; more pairs, more chunks); algorithmic bytes per pair:
+        # 8 child reads, the regular source and the write
+        lv = [(st["coalesced_pairs"], L) for L in range(w.max_level + 1)
+              for st in [lbm.plan_level_stats(w.R, w.n, w.max_level, L, refine=w.refine)] if st["coalesced_pairs"]]
+        groups = {}
+        for path, counter, key in ((sweep_fetch, "FETCH_SIZE", 0), (sweep_write, "WRITE_SIZE", 1)):
+            db = _db(path)
+            first = _measured_from(db)
+            for n, v, g, d in db.execute(
+                    "select p.name, p.counter_value, k.grid_x, k.dispatch_id from pmc_events p join kernels k "
+                    "on p.dispatch_id = k.dispatch_id where p.counter_name = ?", (counter,)):
+                if "coalesce_kernel" in n and d > first:
+                    groups.setdefault(g, ([], []))[key].append(v)
+        for (pairs, L), g in zip(sorted(lv), sorted(groups)):
+            f_, w_ = groups[g]
+            if not f_ or not w_:
+                continue
+            fb = sum(f_) / len(f_) * 1024.0 * fetch_scale
+            wb = sum(w_) / len(w_) * 1024.0 * write_scale
+            fh.write(f"coalesce_level_{L}: pairs {pairs}, fetch_bytes_per_launch {fb:.0f}, "
+                     f"write_bytes_per_launch {wb:.0f}, algorithmic_bytes_per_launch {10 * s * pairs}, "
+                     f"traffic_over_algorithmic {(fb + wb) / (10 * s * pairs):.3f}, launches_averaged {len(f_)}\n")
     print(open(out).read())
 
 
