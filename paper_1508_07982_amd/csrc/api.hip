@@ -119,11 +119,16 @@ int make_levels(int n, size_t s, const std::vector<LevelTables>& tabs, std::vect
                   (unsigned long long)v.plane);
     const size_t bytes = size_t(v.plane) * 19 * s;
     v.nbuf = L == 0 ? 2 : 3;
+    const size_t fbytes = size_t(t.nblocks) * 10 * n * n * s;
     for (int b = 0; b < v.nbuf; ++b) {
       uint8_t* p = nullptr;
       if ((rc = dev_alloc(v.allocs, &p, bytes))) return rc;
       if (bytes) HIP_TRY(hipMemset(p, 0, bytes));
       v.buf[b] = p;
+      p = nullptr;
+      if ((rc = dev_alloc(v.allocs, &p, fbytes))) return rc;
+      if (fbytes) HIP_TRY(hipMemset(p, 0, fbytes));
+      v.xface[b] = p;
     }
     if ((rc = upload(v.allocs, &v.nbr, t.nbr))) return rc;
     if ((rc = upload(v.allocs, &v.flags, t.flags))) return rc;
@@ -139,30 +144,6 @@ int make_levels(int n, size_t s, const std::vector<LevelTables>& tabs, std::vect
       v.coal = p;
       if ((rc = dev_alloc(v.allocs, &p, size_t(t.fine_blocks) * 10 * n * n * s))) return rc;
       v.coal_x = p;
-    }
-    // face rows: the level-L blocks that level L-1's coalescence reads
-    if (L > 0) {
-      std::vector<int32_t> fidx(size_t(t.nblocks), -1), fslot;
-      for (int32_t b : tabs[L - 1].fine_nbr) {
-        if (b < 0) continue;
-        if (b >= t.nblocks) return fail(LBM_E_STATE, "level %zu: fine neighbour %d out of range", L - 1, b);
-        if (fidx[size_t(b)] < 0) {
-          fidx[size_t(b)] = int32_t(fslot.size());
-          fslot.push_back(b);
-        }
-      }
-      v.nface = int32_t(fslot.size());
-      if (v.nface) {
-        if ((rc = upload(v.allocs, &v.face_index, fidx))) return rc;
-        if ((rc = upload(v.allocs, &v.face_slot, fslot))) return rc;
-        const size_t fbytes = size_t(v.nface) * 10 * n * n * s;
-        for (int b = 0; b < v.nbuf; ++b) {
-          uint8_t* p = nullptr;
-          if ((rc = dev_alloc(v.allocs, &p, fbytes))) return rc;
-          HIP_TRY(hipMemset(p, 0, fbytes));
-          v.xface[b] = p;
-        }
-      }
     }
     if ((rc = upload(v.allocs, &v.work, t.work))) return rc;
   }
@@ -182,9 +163,8 @@ void set_level_omegas(lbm_forest* f);
 int refresh_faces(lbm_forest* f) {
   for (size_t L = 0; L < f->lv.size(); ++L) {
     const LevelDev& v = f->lv[L];
-    if (v.nface == 0) continue;
     const int b = f->rot[L];
-    HIP_TRY(launch_face_copy(f->storage, f->n, v.buf[b], v.xface[b], v.face_slot, v.nface, f->stream));
+    HIP_TRY(launch_face_copy(f->storage, f->n, v.buf[b], v.xface[b], v.nblocks, f->stream));
   }
   return LBM_OK;
 }
@@ -201,20 +181,20 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
           std::vector<Op>& ops) {
   const LevelDev& d = f->lv[L];
   const int nlev = int(f->lv.size());
-  const void* cur;
   const void* prev = nullptr;
-  int nb;  // buffer written
+  int cb, nb;  // buffers read and written
   if (L == 0) {
-    cur = d.buf[r[0]];
+    cb = r[0];
     nb = r[0] ^ 1;
   } else if (substep == 1) {
-    cur = d.buf[r[L]];
+    cb = r[L];
     nb = (r[L] + 1) % 3;
   } else {
     prev = d.buf[r[L]];
-    cur = d.buf[(r[L] + 1) % 3];
+    cb = (r[L] + 1) % 3;
     nb = (r[L] + 2) % 3;
   }
+  const void* cur = d.buf[cb];
   void* nxt = d.buf[nb];
   const void* fine0 = nullptr;
   const void* fine1 = nullptr;
@@ -249,8 +229,8 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   a.fine_index = d.fine_index;
   a.coal = d.coal;
   a.coal_x = d.coal_x;
+  a.face_cur = d.xface[cb];
   a.face_out = d.xface[nb];
-  a.face_index = d.face_index;
   a.omega = float(d.omega);
   a.omega64 = d.omega;
   a.err = f->d_err;
@@ -266,7 +246,6 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
     c.coal.out_x = d.coal_x;
     c.coal.fine0_x = fine0_x;
     c.coal.fine1_x = fine1_x;
-    c.coal.fine_face = f->lv[L + 1].face_index;
     c.coal.pairs = d.pairs;
     c.coal.chunks = d.chunks;
     c.coal.nchunks = d.nchunks;
@@ -1069,9 +1048,8 @@ int lbm_set_pdfs(lbm_forest* f, const double* h) {
       HIP_TRY(hipMemcpyAsync(d, h + 19 * off, v.ncells * 19 * sizeof(double), hipMemcpyHostToDevice, f->stream));
       HIP_TRY(launch_set_pdfs(f->storage, f->n, current_buffer_mut(f, int(L)), d, v.ncells, f->stream));
       f->steps_since_state = 0;
-      if (v.nface)
-        HIP_TRY(launch_face_copy(f->storage, f->n, current_buffer(f, int(L)), v.xface[f->rot[L]], v.face_slot,
-                                 v.nface, f->stream));
+      HIP_TRY(launch_face_copy(f->storage, f->n, current_buffer(f, int(L)), v.xface[f->rot[L]], v.nblocks,
+                               f->stream));
       HIP_TRY(hipStreamSynchronize(f->stream));
       return LBM_OK;
     };

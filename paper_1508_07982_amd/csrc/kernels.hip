@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(kCoalThreads) coalesce_kernel(CoalArgs c) {
     const int cx = 2 * (i & (H - 1)), cy = 2 * (j & (H - 1)), cz = 2 * (k & (H - 1));
     // a fine value at the x face it leaves through comes from the x-face copy
     const int xout = EX < 0 ? 0 : N - 1;
-    const bool xcopy = EX != 0 && c.fine1_x != nullptr;
+    const bool xcopy = EX != 0;
     C v[8];
     bool fine[8];
 #pragma unroll
@@ -225,14 +225,12 @@ __global__ void __launch_bounds__(kCoalThreads) coalesce_kernel(CoalArgs c) {
       const S* p = static_cast<const S*>(c.cur);
       if (fy >= 0) {
         const int lx = yx & (N - 1), jk = (yy & (N - 1)) + N * (yz & (N - 1));
-        const int fr = xcopy && lx == xout ? c.fine_face[fy] : -1;
-        p = fr >= 0 ? static_cast<const S*>(c.fine1_x) + xface_index_rt<N>(A, uint32_t(fr), uint32_t(jk))
-                    : static_cast<const S*>(c.fine1) + pdf_index<N>(A, uint32_t(fy), uint32_t(lx + N * jk));
+        p = xcopy && lx == xout ? static_cast<const S*>(c.fine1_x) + xface_index_rt<N>(A, uint32_t(fy), uint32_t(jk))
+                                : static_cast<const S*>(c.fine1) + pdf_index<N>(A, uint32_t(fy), uint32_t(lx + N * jk));
       } else if (fz >= 0) {
         const int lx = zx & (N - 1), jk = (zy & (N - 1)) + N * (zz & (N - 1));
-        const int fr = xcopy && lx == xout ? c.fine_face[fz] : -1;
-        p = fr >= 0 ? static_cast<const S*>(c.fine0_x) + xface_index_rt<N>(A, uint32_t(fr), uint32_t(jk))
-                    : static_cast<const S*>(c.fine0) + pdf_index<N>(A, uint32_t(fz), uint32_t(lx + N * jk));
+        p = xcopy && lx == xout ? static_cast<const S*>(c.fine0_x) + xface_index_rt<N>(A, uint32_t(fz), uint32_t(jk))
+                                : static_cast<const S*>(c.fine0) + pdf_index<N>(A, uint32_t(fz), uint32_t(lx + N * jk));
       }
       fine[q] = fy >= 0 || fz >= 0;
       v[q] = Form<S>::ld(p);
@@ -251,14 +249,14 @@ __global__ void __launch_bounds__(kCoalThreads) coalesce_kernel(CoalArgs c) {
 
 // x-face copy of a buffer (see CoalArgs): one thread per element of xf.
 template <typename S, int N>
-__global__ void face_copy_kernel(const S* buf, S* xf, const int32_t* face_slot, int64_t count) {
+__global__ void face_copy_kernel(const S* buf, S* xf, int64_t count) {
   constexpr int N2 = N * N;
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= count) return;
-  const int64_t row = e / (kXDirs * N2);
+  const int64_t slot = e / (kXDirs * N2);
   const int A = xdir_dir(int((e / N2) % kXDirs));
   const int jk = int(e % N2);
-  xf[e] = buf[pdf_index<N>(A, uint32_t(face_slot[row]), uint32_t((ex(A) < 0 ? 0 : N - 1) + N * jk))];
+  xf[e] = buf[pdf_index<N>(A, uint64_t(slot), uint32_t((ex(A) < 0 ? 0 : N - 1) + N * jk))];
 }
 
 template <typename F>
@@ -378,15 +376,14 @@ hipError_t launch_coalesce(int storage, int n, const CoalArgs& a, hipStream_t st
   });
 }
 
-hipError_t launch_face_copy(int storage, int n, const void* buf, void* xf, const int32_t* face_slot, int32_t nrows,
-                            hipStream_t stream) {
-  if (nrows <= 0) return hipSuccess;
+hipError_t launch_face_copy(int storage, int n, const void* buf, void* xf, int64_t nblocks, hipStream_t stream) {
+  if (nblocks <= 0) return hipSuccess;
   return dispatch(storage, n, [&](auto s, auto nn) {
     using S = decltype(s);
     constexpr int N = decltype(nn)::value;
-    const int64_t count = int64_t(nrows) * kXDirs * N * N;
+    const int64_t count = nblocks * kXDirs * N * N;
     hipLaunchKernelGGL((face_copy_kernel<S, N>), dim3(grid_for(count, 256)), dim3(256), 0, stream,
-                       static_cast<const S*>(buf), static_cast<S*>(xf), face_slot, count);
+                       static_cast<const S*>(buf), static_cast<S*>(xf), count);
     return hipGetLastError();
   });
 }

@@ -28,8 +28,8 @@ struct SweepArgs {
   const int32_t* fine_index;  // [slot]
   const void* coal;           // coalesced values of this substep, [row][19][n^3] (see CoalArgs)
   const void* coal_x;         // the same for the pairs that cross an x face, [row][10][n^2]
-  void* face_out;             // x-face copy of nxt, [face row][10][n^2] (null: not kept)
-  const int32_t* face_index;  // [slot]: face row, -1 for a slot without one
+  const void* face_cur;       // x-face copy of cur, [slot][10][n^2] (see CoalArgs)
+  void* face_out;             // x-face copy of nxt (null: not written)
   float omega;                // omega_L (FP32 arithmetic forms)
   double omega64;             // omega_L (FP64 form)
   int* err;                   // error bits (table lookup failures)
@@ -45,11 +45,12 @@ enum ErrBits : int { kErrNoSource = 1, kErrNoChild = 2 };
 // fine_nbr row), or to out_x for a pair that enters through an x face
 // (cell x = 0 with e_a,x = +1, x = n - 1 with e_a,x = -1; x-face layout).
 //
-// Every level L >= 1 block that a coarser block's fine_nbr lists has a face
-// row: each sweep of level L also writes the values leaving the block
-// through its x faces (cell x = 0 for e_a,x = -1, x = n - 1 for +1) into the
-// x-face copy of the buffer it writes, and the coalescence reads those from
-// the copy (one element per line otherwise).  A buffer written by anything
+// Every state buffer has an x-face copy, [slot][10][n^2]: the values that
+// leave each block through its x faces (cell x = 0 for e_a,x = -1, x = n - 1
+// for +1).  Each sweep writes the copy of the buffer it writes, from
+// registers; the sweep takes the x-edge value of each row end from its x
+// neighbour's copy and the coalescence its children at x faces (one element
+// per 128-byte line in the state's layout).  A buffer written by anything
 // but a sweep has its copy refreshed by launch_face_copy.
 struct CoalArgs {
   const void* cur;            // level-L state read by the following sweep (the regular sources)
@@ -57,9 +58,8 @@ struct CoalArgs {
   const void* fine1;          // level-(L+1) state after its first substep
   void* out;                  // [row][19][n^3]
   void* out_x;                // [row][10][n^2]
-  const void* fine0_x;        // x-face copies of fine0 and fine1 (null: none kept)
+  const void* fine0_x;        // x-face copies of fine0 and fine1
   const void* fine1_x;
-  const int32_t* fine_face;   // level-(L+1) [slot]: face row or -1
   const uint32_t* pairs;      // [pair]: (direction << 16) | cell, grouped by row
   const int32_t* chunks;      // [chunk][3]: row, first pair, end pair
   int32_t nchunks;
@@ -70,10 +70,8 @@ struct CoalArgs {
 
 hipError_t launch_coalesce(int storage, int n, const CoalArgs& a, hipStream_t stream);
 
-// x-face copy of a whole buffer: xf[row] takes the x-face values of block
-// face_slot[row], for rows [0, nrows).
-hipError_t launch_face_copy(int storage, int n, const void* buf, void* xf, const int32_t* face_slot, int32_t nrows,
-                            hipStream_t stream);
+// x-face copy of a whole buffer of nblocks blocks.
+hipError_t launch_face_copy(int storage, int n, const void* buf, void* xf, int64_t nblocks, hipStream_t stream);
 
 // Cells per work tile of the sweep kernel (one workgroup's share).
 int sweep_tile_cells(int storage, int n);

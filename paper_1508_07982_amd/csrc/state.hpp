@@ -31,10 +31,7 @@ struct LevelDev {
   int32_t nchunks = 0;
   void* coal = nullptr;         // coalesced values [fine row][19][n^3]
   void* coal_x = nullptr;       // coalesced values of x-crossing pairs [fine row][10][n^2]
-  void* xface[3] = {nullptr, nullptr, nullptr};  // x-face copy of each buffer [face row][10][n^2]
-  int32_t* face_index = nullptr;  // [slot]: face row or -1
-  int32_t* face_slot = nullptr;   // [face row]: slot
-  int32_t nface = 0;              // face rows: the blocks a coarser level's fine_nbr lists
+  void* xface[3] = {nullptr, nullptr, nullptr};  // x-face copy of each buffer [slot][10][n^2]
   int32_t* work = nullptr;      // work tiles in canonical order
   int persistent = -1;          // launch shape of this level; -1: the forest-wide setting
   int order = 0;                // 0 canonical unit order, 1 XCD-grouped (SweepArgs::xcd)

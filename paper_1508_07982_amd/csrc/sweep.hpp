@@ -39,13 +39,11 @@
 namespace lbm {
 namespace dev {
 
-// Per-workgroup copy of the slot's neighbour table, for a slot with finer
-// neighbours its row in the coalesced-value buffers, and its face row (-1:
-// no x-face copy written).
+// Per-workgroup copy of the slot's neighbour table and, for a slot with
+// finer neighbours, its row in the coalesced-value buffers.
 struct SlotCache {
   int32_t nbr[27];
   int32_t fine_row;
-  int32_t face_row;
 };
 
 // Neighbour offset (-1, 0, +1) of a local coordinate after a shift.
@@ -117,8 +115,10 @@ __device__ __forceinline__ const S* coalesced_source(const SweepArgs& a, const S
 // lane, in two phases so that every load of the lane is in flight before
 // the first one is used:
 //   issue_dir: one vector load of the source row into h[A] and, for
-//              x-shifted directions, one element load into edge[] (every
-//              lane loads, so no branch and no wait splits the loads);
+//              x-shifted directions, one element load into edge[] from the
+//              x neighbour's x-face copy (every lane of a row loads the
+//              row end's element, so no branch and no wait splits the
+//              loads and the row's lanes share one address);
 //   shift_dir: the x shift of the row by one cell, a DPP move between
 //              lanes, with the edge element at the end of the row.
 // A source block that is not a level-L block sets `odd` (the address is
@@ -143,10 +143,10 @@ __device__ __forceinline__ void issue_dir(const SweepArgs& a, const SlotCache& s
     const bool at_end = EX == 1 ? i0 == 0 : i0 == N - W;
     const int nbx = sc.nbr[dmain - EX];
     if (!SIMPLE) odd |= uint32_t(at_end && nbx < 0);
-    // the lane at the end of the row reads the neighbour row's end element,
-    // the others the end element of their own source row (in bounds, unused)
-    const int eb = at_end ? (SIMPLE || nbx >= 0 ? nbx : slot) : (SIMPLE || nbm >= 0 ? nbm : slot);
-    edge[xdir_index(A)] = Form<S>::ld(base + pdf_index<N>(A, uint32_t(eb), row + uint32_t(EX == 1 ? N - 1 : 0)));
+    // the end element of the x neighbour's source row, cell N - 1 (EX = 1)
+    // or 0 (EX = -1): a value leaving that block through its x face
+    const int eb = SIMPLE || nbx >= 0 ? nbx : slot;
+    edge[xdir_index(A)] = Form<S>::ld(static_cast<const S*>(a.face_cur) + xface_index<N, A>(uint32_t(eb), row / N));
   }
 }
 
@@ -343,7 +343,7 @@ __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache&
   S* __restrict__ nxt = static_cast<S*>(a.nxt) + pdf_index<N>(0, uint32_t(slot), uint32_t(cell0));
 #pragma unroll
   for (int d = 0; d < 19; ++d) Vec<S>::store(nxt + d * N3, h[d]);
-  if (sc.face_row >= 0) store_faces<S, N>(a, sc.face_row, i0, j, k, h);
+  if (a.face_out) store_faces<S, N>(a, slot, i0, j, k, h);
 }
 
 // ---- packed FP16 path: 8 cells per lane as 4 registers of half pairs ------
@@ -386,8 +386,8 @@ __device__ __forceinline__ void issue_dir_h8(const SweepArgs& a, const SlotCache
     const bool at_end = EX == 1 ? i0 == 0 : i0 == N - 8;
     const int nbx = sc.nbr[dmain - EX];
     if (!SIMPLE) odd |= uint32_t(at_end && nbx < 0);
-    const int eb = at_end ? (SIMPLE || nbx >= 0 ? nbx : slot) : bms;
-    edge[xdir_index(A)] = base[pdf_index<N>(A, uint32_t(eb), row + uint32_t(EX == 1 ? N - 1 : 0))];
+    const int eb = SIMPLE || nbx >= 0 ? nbx : slot;  // as in issue_dir
+    edge[xdir_index(A)] = static_cast<const uint16_t*>(a.face_cur)[xface_index<N, A>(uint32_t(eb), row / N)];
   }
 }
 
@@ -489,11 +489,11 @@ __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCac
     const u32x4 t = {q[d][0], q[d][1], q[d][2], q[d][3]};
     __builtin_nontemporal_store(t, reinterpret_cast<u32x4*>(nxt + d * N3));
   }
-  if (sc.face_row >= 0) {  // x-face copy (see store_faces)
+  if (a.face_out) {  // x-face copy (see store_faces)
     uint16_t* __restrict__ f = static_cast<uint16_t*>(a.face_out);
     const uint32_t jk = uint32_t(j + N * k);
-    if (i0 == 0) store_face_side_h8<N, -1>(f, uint64_t(sc.face_row), jk, q);
-    if (i0 == N - 8) store_face_side_h8<N, 1>(f, uint64_t(sc.face_row), jk, q);
+    if (i0 == 0) store_face_side_h8<N, -1>(f, uint64_t(slot), jk, q);
+    if (i0 == N - 8) store_face_side_h8<N, 1>(f, uint64_t(slot), jk, q);
   }
 }
 
@@ -520,7 +520,6 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, SlotCache& sc, in
     const int row = fl & kHasFine ? a.fine_index[slot] : 0;
     if (row < 0) atomicOr(a.err, kErrNoChild);
     sc.fine_row = row < 0 ? 0 : row;
-    sc.face_row = a.face_out ? a.face_index[slot] : -1;
   }
   __syncthreads();
   if (fl & kAllSameLevel)
