@@ -46,6 +46,13 @@ def forest_single(n):
     return (2, 3, 2), n, 0, None
 
 
+def forest_narrow(n):
+    """One root wide in x and z (periodic): a level-0 block is its own x
+    neighbour, and the two level-1 blocks of a row are each other's on both
+    sides."""
+    return (1, 3, 1), n, 1, lambda L, x, y, z: L == 0 and (x, y, z) == (0, 0, 0)
+
+
 def rel_l2(a, b, w):
     num = np.sqrt(np.sum(w[:, None] * (a - b).reshape(len(w), -1) ** 2))
     den = np.sqrt(np.sum(w[:, None] * b.reshape(len(w), -1) ** 2))
@@ -69,8 +76,8 @@ def make_pair(spec, storage, omega0, field_seed=3, amp=0.03):
 
 
 @pytest.mark.parametrize("spec", [forest_single(8), forest_two(4), forest_two(8), forest_three(4), forest_three(8),
-                                  forest_three_empty0(4)],
-                         ids=["single8", "two4", "two8", "three4", "three8", "three4_empty0"])
+                                  forest_three_empty0(4), forest_narrow(4), forest_narrow(8)],
+                         ids=["single8", "two4", "two8", "three4", "three8", "three4_empty0", "narrow4", "narrow8"])
 def test_fp64_matches_oracle(spec):
     say(f"fp64 parity {spec[:3]}")
     o, g = make_pair(spec, "f64", 1.45)
