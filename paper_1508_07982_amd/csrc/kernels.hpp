@@ -27,7 +27,7 @@ struct SweepArgs {
   const uint32_t* flags;      // [slot]
   const int32_t* fine_index;  // [slot]
   const void* coal;           // coalesced values of this substep, [row][19][n^3] (see CoalArgs)
-  const void* coal_x;         // the same for the pairs that cross an x face, [row][10][n^2]
+  const void* coal_x;         // the same for the pairs entering through an x face, [row][10][n^2]
   const void* face_cur;       // x-face copy of cur, [slot][10][n^2] (see CoalArgs)
   void* face_out;             // x-face copy of nxt (null: not written)
   float omega;                // omega_L (FP32 arithmetic forms)
@@ -48,10 +48,11 @@ enum ErrBits : int { kErrNoSource = 1, kErrNoChild = 2 };
 // Every state buffer has an x-face copy, [slot][10][n^2]: the values that
 // leave each block through its x faces (cell x = 0 for e_a,x = -1, x = n - 1
 // for +1).  Each sweep writes the copy of the buffer it writes, from
-// registers; the sweep takes the x-edge value of each row end from its x
-// neighbour's copy and the coalescence its children at x faces (one element
-// per 128-byte line in the state's layout).  A buffer written by anything
-// but a sweep has its copy refreshed by launch_face_copy.
+// registers.  The sweep takes the x-edge value of each row end from its x
+// neighbour's copy, and the coalescence its children at x faces; in the
+// state's layout each of these would cost a 128-byte line per element.  A
+// buffer written by anything but a sweep has its copy refreshed by
+// launch_face_copy.
 struct CoalArgs {
   const void* cur;            // level-L state read by the following sweep (the regular sources)
   const void* fine0;          // level-(L+1) state at the start of the parent step
