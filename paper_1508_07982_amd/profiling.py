@@ -25,6 +25,7 @@ import csv
 import glob
 import hashlib
 import os
+import re
 import sqlite3
 import sys
 
@@ -34,10 +35,14 @@ COPY_BYTES = 1 << 30
 
 
 def sweep_sources_hash(storage: str = "f32") -> str:
+    """Hash of the sweep kernel's sources with comments and blank space
+    removed, so that a counter summary stays valid across comment edits."""
     h = hashlib.sha256()
     for f in ("sweep.hpp", "lattice.hpp", "kernels.hpp", f"sweep_{storage}.hip"):
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
+        code = [" ".join(line.split("//", 1)[0].split()) for line in text.splitlines()]
+        h.update("\n".join(c for c in code if c).encode())
     return h.hexdigest()[:16]
 
 
