@@ -148,7 +148,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-forms", action="store_true", help="skip the FP16 and per-block comparison runs")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP16, FP64 and per-block comparison runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -203,6 +203,19 @@ def main():
                               "launch": launch_table(launch16), "mass_drift": abs(M16b - M16a) / M16a}
         g16.close()
         del g16
+        g64 = make_forest(lbm, W, w, "f64", stream.cuda_stream)
+        launch64 = g64.autotune(1)
+        g64.step_coarse(1)
+        M64a, _ = g64.mass()
+        ms64 = timed_steps(torch, g64, stream, 3)
+        M64b, _ = g64.mass()
+        sw64, co64 = g64.time_launches(1)
+        forms["f64_graph"] = {"MLUPS": round(upd / (ms64 * 1e-3) / 1e6, 1), "ms_per_step": round(ms64, 3),
+                              "roofline_MLUPS": round(HBM_PEAK_GBS * 1e9 / (38 * 8) / 1e6, 1),
+                              "per_level": level_table(g64, sw64, 8, co64),
+                              "launch": launch_table(launch64), "mass_drift": abs(M64b - M64a) / M64a}
+        g64.close()
+        del g64
         forms["batching_slab_sphere"] = batching_form(torch, lbm, W, stream)
         gp = make_forest(lbm, W, w, "f32", stream.cuda_stream)
         gp.set_schedule("per_block")
