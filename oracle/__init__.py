@@ -30,5 +30,6 @@ Readings of the paper taken here (its figures are lost, some formulas are
 garbled) are listed in the module docstrings where they are used.
 """
 
-from .refined import RefinedOracle, omega_level, lattice, equilibrium, collide  # noqa: F401
+from .refined import (RefinedOracle, omega_level, lattice, equilibrium, collide, collide_trt,  # noqa: F401
+                      lambda_o_level, accel_level)
 from .forest import Forest  # noqa: F401

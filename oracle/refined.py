@@ -30,6 +30,9 @@ class _Level(ctypes.Structure):
         ("coal_cell", ctypes.c_void_p), ("coal_dir", ctypes.c_void_p), ("coal_child", ctypes.c_void_p),
         ("omega", ctypes.c_double),
         ("poison_far", ctypes.c_int),
+        ("trt", ctypes.c_int),
+        ("lambda_o", ctypes.c_double),
+        ("accel", ctypes.c_double * 3),
     ]
 
 
@@ -45,6 +48,8 @@ def _load():
         for name in ("orc_equilibrium", "orc_moments"):
             getattr(lib, name).argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_collide.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_double]
+        lib.orc_collide_trt.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_void_p]
         lib.orc_lattice.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_stream_calls.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
         if lib.orc_sizeof_level() != ctypes.sizeof(_Level):
@@ -90,6 +95,26 @@ def collide(f, omega: float) -> np.ndarray:
     return f
 
 
+def collide_trt(f, lambda_e: float, lambda_o: float, accel=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """One TRT collision with a body force (section 2) of every row of f
+    (N, 19); returns a new array."""
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    a = np.ascontiguousarray(accel, dtype=np.float64)
+    _load().orc_collide_trt(len(f), _ptr(f), float(lambda_e), float(lambda_o), _ptr(a))
+    return f
+
+
+def lambda_o_level(lambda_e, lambda_eo):
+    """eq. lambda_oL: the odd rate that keeps Lambda_eo (eq. lambda_eo) at
+    the given value for the even rate lambda_e.  Exact for Fractions."""
+    return (4 - 2 * lambda_e) / (2 + (4 * lambda_eo - 1) * lambda_e)
+
+
+def accel_level(accel0, L: int):
+    """eq. force_scaling: a_L = a_0 / 2^L (lattice units of level L)."""
+    return [a / 2 ** L for a in accel0]
+
+
 def omega_level(omega0, L: int):
     """eq. omega_scaling_0: omega_L = 2 w0 / (2^(L+1) + (1 - 2^L) w0).
     Exact if omega0 is a Fraction."""
@@ -100,7 +125,12 @@ def omega_level(omega0, L: int):
 class RefinedOracle:
     """FP64 Algorithm-1 oracle on a 2:1 balanced forest."""
 
-    def __init__(self, forest: Forest, omega0: float, coalescence: str = "virtual"):
+    def __init__(self, forest: Forest, omega0: float, coalescence: str = "virtual", lambda_eo=None,
+                 accel0=None):
+        """omega0: SRT omega_0, or with lambda_eo (TRT) the even rate
+        lambda_e,0, scaled per level by eq. omega_scaling_0.  lambda_eo: TRT
+        with lambda_o,L from eq. lambda_oL; accel0: constant lattice
+        acceleration of level 0 (force term, a_L by eq. force_scaling)."""
         self.forest = forest
         self.n = forest.n
         self.num_levels = forest.max_level + 1
@@ -108,6 +138,10 @@ class RefinedOracle:
         self._omega0 = omega0
         self._coalescence = coalescence
         self.omega = [float(omega_level(float(omega0), L)) for L in range(self.num_levels)]
+        self.trt = lambda_eo is not None or accel0 is not None
+        self.lambda_o = [float(lambda_o_level(w, lambda_eo)) if lambda_eo is not None else w for w in self.omega]
+        a0 = [float(a) for a in (accel0 if accel0 is not None else (0.0, 0.0, 0.0))]
+        self.accel = [accel_level(a0, L) for L in range(self.num_levels)]
         self.F = []
         self.G = []
         for t in self.tables:
@@ -166,6 +200,9 @@ class RefinedOracle:
             lv.coal_child = _ptr(t.coal_child)
             lv.omega = self.omega[L]
             lv.poison_far = int(self.poison_far)
+            lv.trt = int(self.trt)
+            lv.lambda_o = self.lambda_o[L]
+            lv.accel = (ctypes.c_double * 3)(*self.accel[L])
         self._levels = arr
 
     def step(self, steps: int = 1):
@@ -185,6 +222,8 @@ class RefinedOracle:
         oracle/regrid.py); omega_0 and the coalescence reading are kept."""
         from .regrid import regrid_forest, remap_interior
         nf = regrid_forest(self.forest, flags, max_level)
+        if self.trt:
+            raise NotImplementedError("regrid of a TRT / forced state")
         new = RefinedOracle(nf, self._omega0, self._coalescence)
         pdfs = remap_interior(self.forest, [self.interior_pdfs(L) for L in range(self.num_levels)], nf)
         for L in range(new.num_levels):
@@ -194,12 +233,14 @@ class RefinedOracle:
 
     # -- outputs -------------------------------------------------------------
     def moments(self):
-        """(rho (N,), u (N, 3)) over all interior cells in canonical order."""
+        """(rho (N,), u (N, 3)) over all interior cells in canonical order;
+        with a body force u = sum e f / rho0 + a_L / 2 (section 2, external
+        forces)."""
         rs, us = [], []
         for L in range(self.num_levels):
             r, u = moments(self.interior_pdfs(L))
             rs.append(r)
-            us.append(u)
+            us.append(u + 0.5 * np.asarray(self.accel[L])[None, :])
         return np.concatenate(rs), np.concatenate(us)
 
     def level_weights(self) -> np.ndarray:

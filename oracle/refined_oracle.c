@@ -12,6 +12,11 @@
  *                 (the printed formula sums f^eq, which is circular; after a
  *                 collision both readings agree)
  *   collide       SRT:  f <- f - omega (f - f^eq)           (section 2)
+ *                 or TRT with a constant body force (section 2, TRT
+ *                 model and external forces): the even and odd parts of
+ *                 f - f^eq relax with lambda_e and lambda_o, then
+ *                 F_a = w_a rho0 (e_a . a) / c_s^2 is added; u in f^eq is
+ *                 the unmodified sum e f / rho0
  *   explode       eq. ctof: every E_L cell takes its parent's 19 PDFs
  *   stream        pull: f(x) <- f(x - e_a) for x in I_L u H_L (eq. stream)
  *   coalesce      eq. ftoc: 1/8 of the sum over the 8 children, for the
@@ -58,8 +63,11 @@ typedef struct {
   const int32_t *coal_cell;   /* n_coal */
   const int32_t *coal_dir;    /* n_coal */
   const int32_t *coal_child;  /* n_coal x 8 */
-  double omega;
+  double omega;     /* SRT omega_L, or TRT lambda_e,L                  */
   int poison_far;   /* debug: overwrite E_L \ H_L with NaN after explosion */
+  int trt;          /* 1: TRT + force collision with the two fields below */
+  double lambda_o;  /* TRT odd rate lambda_o,L                          */
+  double accel[3];  /* lattice acceleration a_L of this level           */
 } orc_level;
 
 void orc_lattice(int32_t *e, double *w) {
@@ -113,7 +121,35 @@ void orc_collide(int64_t n, double *f, double omega) {
   }
 }
 
-static void collide(orc_level *lv) { orc_collide(lv->n_int, lv->F, lv->omega); }
+/* TRT collision with a body force, one cell after another: with abar the
+   direction opposite to a, f+- = (f_a +- f_abar) / 2 and the same for f^eq,
+   f_a <- f_a - lambda_e (f+ - f^eq+) - lambda_o (f- - f^eq-) + F_a,
+   F_a = w_a rho0 (e_a . accel) / c_s^2 with c_s^2 = 1/3. */
+void orc_collide_trt(int64_t n, double *f, double lambda_e, double lambda_o, const double accel[3]) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double rho, u[3], eq[Q], out[Q];
+    double *fi = f + Q * i;
+    moments_cell(fi, &rho, u);
+    feq_cell(rho, u, eq);
+    for (int a = 0; a < Q; ++a) {
+      int ab = 0;  /* the opposite direction */
+      while (EV[ab][0] != -EV[a][0] || EV[ab][1] != -EV[a][1] || EV[ab][2] != -EV[a][2]) ++ab;
+      const double fp = 0.5 * (fi[a] + fi[ab]), fm = 0.5 * (fi[a] - fi[ab]);
+      const double ep = 0.5 * (eq[a] + eq[ab]), em = 0.5 * (eq[a] - eq[ab]);
+      const double ea = EV[a][0] * accel[0] + EV[a][1] * accel[1] + EV[a][2] * accel[2];
+      out[a] = fi[a] - lambda_e * (fp - ep) - lambda_o * (fm - em) + weight(a) * RHO0 * ea * 3.0;
+    }
+    for (int a = 0; a < Q; ++a) fi[a] = out[a];
+  }
+}
+
+static void collide(orc_level *lv) {
+  if (lv->trt)
+    orc_collide_trt(lv->n_int, lv->F, lv->omega, lv->lambda_o, lv->accel);
+  else
+    orc_collide(lv->n_int, lv->F, lv->omega);
+}
 
 static void explode(orc_level *lv, const orc_level *coarse) {
   const int64_t m = lv->n_store - lv->n_int;
