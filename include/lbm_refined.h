@@ -134,6 +134,22 @@ int lbm_level_stats(const lbm_forest *f, int level, int64_t out[8]);
 int lbm_set_level_omega(lbm_forest *f, double omega0);
 int lbm_get_level_omega(const lbm_forest *f, int level, double *omega);
 
+/* TRT collision and a constant body force (section 2, TRT model and
+ * external forces).  omega_L of lbm_set_level_omega becomes the even rate
+ * lambda_e,L; lambda_eo > 0 is Lambda_eo of eq. lambda_eo, kept on every
+ * level by lambda_o,L from eq. lambda_oL (lambda_eo == 0: lambda_o = lambda_e).
+ * accel0[3] (host, may be NULL for none) is the lattice acceleration a_0* of
+ * level 0; level L uses a_0* / 2^L (eq. force_scaling) and adds
+ * F_a = 3 w_a e_a . a_L after each collision, with u in f^eq the plain sum
+ * e f.  lambda_eo == 0 with no acceleration restores SRT.  Call before
+ * lbm_init_pdfs (the stored state is post-collision: lbm_init_pdfs adds the
+ * force term of one collision), and lbm_get_moments then reports
+ * u = sum e f / rho0 + a_L / 2 of the pre-collision state.  lbm_regrid
+ * refuses a forest with TRT or a force (LBM_E_STATE).
+ * Errors: LBM_E_INVALID (null handle, lambda_eo < 0 or not finite, a
+ * non-finite acceleration). */
+int lbm_set_trt_force(lbm_forest *f, double lambda_eo, const double accel0[3]);
+
 /* f = f^eq(rho, u) (eq. fequ) on every interior cell.  rho[N], u[N][3],
  * host FP64 in canonical order, N = lbm_num_cells(-1).  Synchronous. */
 int lbm_init_pdfs(lbm_forest *f, const double *rho, const double *u);

@@ -234,6 +234,13 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   a.omega = float(d.omega);
   a.omega64 = d.omega;
   a.err = f->d_err;
+  a.trt = f->trt ? 1 : 0;
+  a.lambda_o = float(d.lambda_o);
+  a.lambda_o64 = d.lambda_o;
+  for (int q = 0; q < 3; ++q) {
+    a.accel[q] = float(d.accel[q]);
+    a.accel64[q] = d.accel[q];
+  }
   if (L + 1 < nlev && d.nchunks > 0) {
     Op c;
     c.level = L;
@@ -313,9 +320,20 @@ int capture_graph(lbm_forest* f, const std::vector<Op>& ops, hipGraphExec_t* out
 
 void set_level_omegas(lbm_forest* f) {
   for (size_t L = 0; L < f->lv.size(); ++L) {
+    LevelDev& v = f->lv[L];
     const double p = std::ldexp(1.0, int(L));
-    f->lv[L].omega = 2.0 * f->omega0 / (2.0 * p + (1.0 - p) * f->omega0);  // eq. omega_scaling_0
+    v.omega = 2.0 * f->omega0 / (2.0 * p + (1.0 - p) * f->omega0);  // eq. omega_scaling_0
+    // TRT: lambda_e,L = omega_L, lambda_o,L by eq. lambda_oL; a_L by eq. force_scaling
+    v.lambda_o = f->lambda_eo > 0.0 ? (4.0 - 2.0 * v.omega) / (2.0 + (4.0 * f->lambda_eo - 1.0) * v.omega) : v.omega;
+    for (int d = 0; d < 3; ++d) v.accel[d] = f->accel0[d] / p;
   }
+}
+
+Accel level_accel(const lbm_forest* f, int L) {
+  Accel a{{0.0, 0.0, 0.0}};
+  if (f->trt)
+    for (int d = 0; d < 3; ++d) a.a[d] = f->lv[L].accel[d];
+  return a;
 }
 
 int check_err_flag(lbm_forest* f) {
@@ -535,6 +553,22 @@ int lbm_set_level_omega(lbm_forest* f, double omega0) {
   return LBM_OK;
 }
 
+int lbm_set_trt_force(lbm_forest* f, double lambda_eo, const double* accel0) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  if (!(lambda_eo >= 0.0) || !std::isfinite(lambda_eo)) return fail(LBM_E_INVALID, "lambda_eo must be finite and >= 0");
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < 3 && accel0; ++d) {
+    if (!std::isfinite(accel0[d])) return fail(LBM_E_INVALID, "acceleration must be finite");
+    a[d] = accel0[d];
+  }
+  f->lambda_eo = lambda_eo;
+  for (int d = 0; d < 3; ++d) f->accel0[d] = a[d];
+  f->trt = lambda_eo > 0.0 || a[0] != 0.0 || a[1] != 0.0 || a[2] != 0.0;
+  set_level_omegas(f);
+  invalidate_graphs(f);
+  return LBM_OK;
+}
+
 int lbm_get_level_omega(const lbm_forest* f, int level, double* omega) {
   if (!f || !omega) return fail(LBM_E_INVALID, "null pointer");
   if (level < 0 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
@@ -565,7 +599,8 @@ int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
     f->steps_since_state = 0;
     for (size_t L = 0; L < f->lv.size(); ++L) {
       const LevelDev& v = f->lv[L];
-      HIP_TRY(launch_init(f->storage, f->n, v.buf[0], d_rho + off, d_u + 3 * off, v.ncells, f->stream));
+      HIP_TRY(launch_init(f->storage, f->n, v.buf[0], d_rho + off, d_u + 3 * off, v.ncells, level_accel(f, int(L)),
+                          f->stream));
       off += v.ncells;
     }
     int rc2 = refresh_faces(f);
@@ -806,6 +841,7 @@ int lbm_time_launches(lbm_forest* f, int n_steps, double* ms, int64_t* launches,
 
 int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
   if (!f || (!flags && count)) return fail(LBM_E_INVALID, "null pointer");
+  if (f->trt) return fail(LBM_E_STATE, "regrid supports the SRT collision without a body force");
   HIP_TRY(hipSetDevice(f->device));
   int rc = check_err_flag(f);
   if (rc) return rc;
@@ -997,7 +1033,8 @@ int lbm_get_moments(lbm_forest* f, double* rho, double* u) {
     double* d = nullptr;
     HIP_TRY(hipMalloc(&d, v.ncells * 4 * sizeof(double)));
     auto body = [&]() -> int {
-      HIP_TRY(launch_moments(f->storage, f->n, current_buffer(f, int(L)), d, d + v.ncells, v.ncells, f->stream));
+      HIP_TRY(launch_moments(f->storage, f->n, current_buffer(f, int(L)), d, d + v.ncells, v.ncells,
+                             level_accel(f, int(L)), f->stream));
       HIP_TRY(hipMemcpyAsync(rho + off, d, v.ncells * sizeof(double), hipMemcpyDeviceToHost, f->stream));
       HIP_TRY(hipMemcpyAsync(u + 3 * off, d + v.ncells, v.ncells * 3 * sizeof(double), hipMemcpyDeviceToHost,
                              f->stream));

@@ -25,7 +25,7 @@ using namespace dev;
 // ---- init / moments / raw I/O / reductions -------------------------------
 
 template <typename S, int N>
-__global__ void init_kernel(S* buf, const double* rho, const double* u, int64_t ncells) {
+__global__ void init_kernel(S* buf, const double* rho, const double* u, int64_t ncells, Accel acc) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= ncells) return;
   const double r = rho[idx], ux = u[3 * idx], uy = u[3 * idx + 1], uz = u[3 * idx + 2];
@@ -33,13 +33,14 @@ __global__ void init_kernel(S* buf, const double* rho, const double* u, int64_t 
 #pragma unroll
   for (int a = 0; a < 19; ++a) {
     const double eu = ex(a) * ux + ey(a) * uy + ez(a) * uz;
-    const double h = wgt<double>(a) * ((r - 1.0) + 3.0 * eu + 4.5 * eu * eu - usq);
+    const double ea = ex(a) * acc.a[0] + ey(a) * acc.a[1] + ez(a) * acc.a[2];
+    const double h = wgt<double>(a) * ((r - 1.0) + 3.0 * eu + 4.5 * eu * eu - usq) + 3.0 * wgt<double>(a) * ea;
     Form<S>::st(buf + pdf_at<N>(a, idx), typename Form<S>::C(h));
   }
 }
 
 template <typename S, int N>
-__global__ void moments_kernel(const S* buf, double* rho, double* u, int64_t ncells) {
+__global__ void moments_kernel(const S* buf, double* rho, double* u, int64_t ncells, Accel acc) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= ncells) return;
   double s = 0, jx = 0, jy = 0, jz = 0;
@@ -52,9 +53,9 @@ __global__ void moments_kernel(const S* buf, double* rho, double* u, int64_t nce
     jz += ez(a) * h;
   }
   rho[idx] = 1.0 + s;
-  u[3 * idx] = jx;
-  u[3 * idx + 1] = jy;
-  u[3 * idx + 2] = jz;
+  u[3 * idx] = jx - 0.5 * acc.a[0];
+  u[3 * idx + 1] = jy - 0.5 * acc.a[1];
+  u[3 * idx + 2] = jz - 0.5 * acc.a[2];
 }
 
 template <typename S, int N>
@@ -309,25 +310,25 @@ hipError_t launch_sweep(int storage, int n, const SweepArgs& a, int grid, int sp
 }
 
 hipError_t launch_init(int storage, int n, void* buf, const double* rho, const double* u,
-                       int64_t ncells, hipStream_t stream) {
+                       int64_t ncells, Accel accel, hipStream_t stream) {
   if (ncells <= 0) return hipSuccess;
   return dispatch(storage, n, [&](auto s, auto nn) {
     using S = decltype(s);
     constexpr int N = decltype(nn)::value;
     hipLaunchKernelGGL((init_kernel<S, N>), dim3(grid_for(ncells, 256)), dim3(256), 0, stream, static_cast<S*>(buf),
-                       rho, u, ncells);
+                       rho, u, ncells, accel);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_moments(int storage, int n, const void* buf, double* rho, double* u,
-                          int64_t ncells, hipStream_t stream) {
+                          int64_t ncells, Accel accel, hipStream_t stream) {
   if (ncells <= 0) return hipSuccess;
   return dispatch(storage, n, [&](auto s, auto nn) {
     using S = decltype(s);
     constexpr int N = decltype(nn)::value;
     hipLaunchKernelGGL((moments_kernel<S, N>), dim3(grid_for(ncells, 256)), dim3(256), 0, stream,
-                       static_cast<const S*>(buf), rho, u, ncells);
+                       static_cast<const S*>(buf), rho, u, ncells, accel);
     return hipGetLastError();
   });
 }

@@ -30,9 +30,14 @@ struct SweepArgs {
   const void* coal_x;         // the same for the pairs entering through an x face, [row][10][n^2]
   const void* face_cur;       // x-face copy of cur, [slot][10][n^2] (see CoalArgs)
   void* face_out;             // x-face copy of nxt (null: not written)
-  float omega;                // omega_L (FP32 arithmetic forms)
+  float omega;                // omega_L (FP32 arithmetic forms); lambda_e,L with trt
   double omega64;             // omega_L (FP64 form)
   int* err;                   // error bits (table lookup failures)
+  int32_t trt;                // 1: TRT collision with a body force (the fields below)
+  float lambda_o;             // lambda_o,L (FP32 arithmetic forms)
+  double lambda_o64;          // lambda_o,L (FP64 form)
+  float accel[3];             // lattice acceleration a_L (FP32 arithmetic forms)
+  double accel64[3];          // a_L (FP64 form)
 };
 
 enum ErrBits : int { kErrNoSource = 1, kErrNoChild = 2 };
@@ -89,13 +94,21 @@ hipError_t launch_sweep(int storage, int n, const SweepArgs& a, int grid, int sp
 // The helpers below address the interior cells [0, ncells) of one level
 // (block-major buffer: element (a, slot, cell) at (19 slot + a) n^3 + cell).
 
-// h = f^eq(rho, u) - w.
-hipError_t launch_init(int storage, int n, void* buf, const double* rho, const double* u,
-                       int64_t ncells, hipStream_t stream);
+// Lattice acceleration of one level (zero: no body force).
+struct Accel {
+  double a[3];
+};
 
-// rho = 1 + sum h, u = sum e h.
+// h = f^eq(rho, u) - w, plus the force term F_a = 3 w_a e_a . a of a
+// collision: the stored state is post-collision, and collision leaves an
+// equilibrium unchanged apart from the force.
+hipError_t launch_init(int storage, int n, void* buf, const double* rho, const double* u,
+                       int64_t ncells, Accel accel, hipStream_t stream);
+
+// rho = 1 + sum h, u = sum e h - a / 2: the velocity of the pre-collision
+// state (sum e h - a) plus a / 2 (section 2, external forces).
 hipError_t launch_moments(int storage, int n, const void* buf, double* rho, double* u,
-                          int64_t ncells, hipStream_t stream);
+                          int64_t ncells, Accel accel, hipStream_t stream);
 
 // Raw shifted PDFs, FP64 [cell][19].
 hipError_t launch_get_pdfs(int storage, int n, const void* buf, double* h, int64_t ncells,

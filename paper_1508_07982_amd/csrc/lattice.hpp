@@ -105,6 +105,8 @@ struct Form<double> {
   static __device__ __forceinline__ double ld(const double* p) { return *p; }
   static __device__ __forceinline__ void st(double* p, double v) { *p = v; }
   static __device__ __forceinline__ double omega(const SweepArgs& a) { return a.omega64; }
+  static __device__ __forceinline__ double lambda_o(const SweepArgs& a) { return a.lambda_o64; }
+  static __device__ __forceinline__ double accel(const SweepArgs& a, int d) { return a.accel64[d]; }
 };
 template <>
 struct Form<float> {
@@ -112,6 +114,8 @@ struct Form<float> {
   static __device__ __forceinline__ float ld(const float* p) { return *p; }
   static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
   static __device__ __forceinline__ float omega(const SweepArgs& a) { return a.omega; }
+  static __device__ __forceinline__ float lambda_o(const SweepArgs& a) { return a.lambda_o; }
+  static __device__ __forceinline__ float accel(const SweepArgs& a, int d) { return a.accel[d]; }
 };
 template <>
 struct Form<__half> {
@@ -119,6 +123,8 @@ struct Form<__half> {
   static __device__ __forceinline__ float ld(const __half* p) { return __half2float(*p); }
   static __device__ __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(v); }
   static __device__ __forceinline__ float omega(const SweepArgs& a) { return a.omega; }
+  static __device__ __forceinline__ float lambda_o(const SweepArgs& a) { return a.lambda_o; }
+  static __device__ __forceinline__ float accel(const SweepArgs& a, int d) { return a.accel[d]; }
 };
 
 // ---- vector access: W consecutive cells of one row per lane ----------------

@@ -36,7 +36,9 @@ struct LevelDev {
   int persistent = -1;          // launch shape of this level; -1: the forest-wide setting
   int order = 0;                // 0 canonical unit order, 1 XCD-grouped (SweepArgs::xcd)
   int split = 1;                // workgroups per work tile (1, 2 or 4; see sweep_split)
-  double omega = 0.0;
+  double omega = 0.0;           // omega_L (SRT) or lambda_e,L (TRT)
+  double lambda_o = 0.0;        // lambda_o,L (TRT)
+  double accel[3] = {0.0, 0.0, 0.0};  // lattice acceleration a_L
   std::vector<void*> allocs;  // device memory owned by this level
 };
 
@@ -73,6 +75,9 @@ struct lbm_forest {
   int64_t steps_since_state = 0;  // coarse steps since the state was set (init, set_pdfs, regrid)
   int max_level = 0;              // deepest level a regrid may create
   double omega0 = 0.0;
+  bool trt = false;               // TRT collision with a body force (lbm_set_trt_force)
+  double lambda_eo = 0.0;         // Lambda_eo of eq. lambda_eo (<= 0: lambda_o = lambda_e)
+  double accel0[3] = {0.0, 0.0, 0.0};  // lattice acceleration of level 0
   std::map<std::vector<int>, hipGraphExec_t> graphs;
   int* d_err = nullptr;
   double* d_partials = nullptr;

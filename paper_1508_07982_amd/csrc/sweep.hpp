@@ -326,7 +326,57 @@ __device__ __forceinline__ void store_faces(const SweepArgs& a, int row, int i0,
   if (i0 == N - Geo<S, N>::W) store_face_side<S, N, 1>(f, uint64_t(row), jk, h);
 }
 
-template <typename S, int N, bool SIMPLE>
+// TRT collision with a constant body force (section 2, TRT model and
+// external forces) of cell c, in shifted form.  For the opposite pair
+// (A, A + 1) the even and odd parts of h - h_eq relax with lambda_e and
+// lambda_o, h_eq+ = w (drho - 1.5 u^2 + 4.5 t^2), h_eq- = 3 w t with
+// t = e_A . u, and F_A = 3 w_A e_A . a is added (F_{A+1} = -F_A):
+//   h_A     <- h_A     - lambda_e (h+ - h_eq+) - [lambda_o (h- - h_eq-) - F_A]
+//   h_{A+1} <- h_{A+1} - lambda_e (h+ - h_eq+) + [lambda_o (h- - h_eq-) - F_A].
+// u in h_eq is the unmodified sum e h.
+template <typename C, int W, int A = 1>
+__device__ __forceinline__ void relax_pairs_trt(C (*h)[W], int c, C base, C ux, C uy, C uz, C le, C lo, C ax, C ay,
+                                                C az) {
+  const C w = wgt<C>(A);
+  C t = C(0), ta = C(0);
+  if constexpr (ex(A) != 0) t += ex(A) > 0 ? ux : -ux, ta += ex(A) > 0 ? ax : -ax;
+  if constexpr (ey(A) != 0) t += ey(A) > 0 ? uy : -uy, ta += ey(A) > 0 ? ay : -ay;
+  if constexpr (ez(A) != 0) t += ez(A) > 0 ? uz : -uz, ta += ez(A) > 0 ? az : -az;
+  const C hp = C(0.5) * (h[A][c] + h[A + 1][c]);
+  const C hm = C(0.5) * (h[A][c] - h[A + 1][c]);
+  const C dp = le * (hp - w * (base + C(4.5) * t * t));
+  const C dm = lo * (hm - C(3) * w * t) - C(3) * w * ta;
+  h[A][c] = h[A][c] - dp - dm;
+  h[A + 1][c] = h[A + 1][c] - dp + dm;
+  if constexpr (A + 2 < 19) relax_pairs_trt<C, W, A + 2>(h, c, base, ux, uy, uz, le, lo, ax, ay, az);
+}
+template <typename C, int W>
+__device__ __forceinline__ void collide_trt(C (*h)[W], int c, C le, C lo, C ax, C ay, C az) {
+  C drho = h[0][c], ux = C(0), uy = C(0), uz = C(0);
+#pragma unroll
+  for (int a = 1; a < 19; a += 2) {
+    drho += h[a][c] + h[a + 1][c];
+    const C d = h[a][c] - h[a + 1][c];
+    if (ex(a)) ux += ex(a) > 0 ? d : -d;
+    if (ey(a)) uy += ey(a) > 0 ? d : -d;
+    if (ez(a)) uz += ez(a) > 0 ? d : -d;
+  }
+  const C base = drho - C(1.5) * (ux * ux + uy * uy + uz * uz);
+  h[0][c] = h[0][c] - le * (h[0][c] - wgt<C>(0) * base);
+  relax_pairs_trt<C, W>(h, c, base, ux, uy, uz, le, lo, ax, ay, az);
+}
+
+// The collision of cell c: SRT, or TRT with the body force.
+template <typename S, bool TRT, typename C, int W>
+__device__ __forceinline__ void collide_cell(const SweepArgs& a, C (*h)[W], int c) {
+  if constexpr (TRT)
+    collide_trt<C, W>(h, c, C(Form<S>::omega(a)), C(Form<S>::lambda_o(a)), C(Form<S>::accel(a, 0)),
+                      C(Form<S>::accel(a, 1)), C(Form<S>::accel(a, 2)));
+  else
+    collide<C, W>(h, c, C(Form<S>::omega(a)));
+}
+
+template <typename S, int N, bool SIMPLE, bool TRT>
 __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl, int cell0) {
   using C = typename Form<S>::C;
   constexpr int W = Geo<S, N>::W, N3 = Geo<S, N>::N3;
@@ -336,9 +386,8 @@ __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache&
   pull_all<S, N, SIMPLE>(a, sc, slot, i0, j, k, h, odd);
   if (!SIMPLE && odd) fixups<S, N>(a, sc, nbr_masks(sc), fl, i0, j, k, h);
   if (a.collide) {
-    const C om = Form<S>::omega(a);
 #pragma unroll
-    for (int c = 0; c < W; ++c) collide<C, W>(h, c, om);
+    for (int c = 0; c < W; ++c) collide_cell<S, TRT>(a, h, c);
   }
   S* __restrict__ nxt = static_cast<S*>(a.nxt) + pdf_index<N>(0, uint32_t(slot), uint32_t(cell0));
 #pragma unroll
@@ -459,7 +508,7 @@ __device__ __forceinline__ void store_face_side_h8(uint16_t* __restrict__ f, uin
   if constexpr (A + 1 < 19) store_face_side_h8<N, SIDE, A + 1>(f, row, jk, q);
 }
 
-template <int N, bool SIMPLE>
+template <int N, bool SIMPLE, bool TRT>
 __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl,
                                                int cell0) {
   constexpr int N3 = N * N * N;
@@ -471,14 +520,13 @@ __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCac
   shift_all_h8<N>(i0, q, edge);
   if (!SIMPLE && odd) fixups_h8<N>(a, sc, nbr_masks(sc), fl, i0, j, k, q);
   if (a.collide) {
-    const float om = a.omega;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       float h[19][2];
 #pragma unroll
       for (int d = 0; d < 19; ++d) h[d][0] = half_lo(q[d][p]), h[d][1] = half_hi(q[d][p]);
-      collide<float, 2>(h, 0, om);
-      collide<float, 2>(h, 1, om);
+      collide_cell<__half, TRT>(a, h, 0);
+      collide_cell<__half, TRT>(a, h, 1);
 #pragma unroll
       for (int d = 0; d < 19; ++d) q[d][p] = pack_pair(h[d][0], h[d][1]);
     }
@@ -497,18 +545,18 @@ __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCac
   }
 }
 
-template <typename S, int N, bool SIMPLE>
+template <typename S, int N, bool SIMPLE, bool TRT>
 __device__ __forceinline__ void update_any(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl, int cell0) {
   if constexpr (Geo<S, N>::PACKED)
-    update_lane_h8<N, SIMPLE>(a, sc, slot, fl, cell0);
+    update_lane_h8<N, SIMPLE, TRT>(a, sc, slot, fl, cell0);
   else
-    update_lane<S, N, SIMPLE>(a, sc, slot, fl, cell0);
+    update_lane<S, N, SIMPLE, TRT>(a, sc, slot, fl, cell0);
 }
 
 // Work unit w: part w % SPLIT of work tile w / SPLIT (a tile split into
 // SPLIT consecutive runs of whole rows, one per workgroup of T / SPLIT
 // lanes).
-template <typename S, int N, int SPLIT>
+template <typename S, int N, int SPLIT, bool TRT>
 __device__ __forceinline__ void sweep_item(const SweepArgs& a, SlotCache& sc, int w) {
   constexpr int W = Geo<S, N>::W, CELLS = Geo<S, N>::CELLS, TPB = Geo<S, N>::TPB;
   const int item = a.work[w / SPLIT];
@@ -523,9 +571,9 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, SlotCache& sc, in
   }
   __syncthreads();
   if (fl & kAllSameLevel)
-    update_any<S, N, true>(a, sc, slot, fl, cell0);
+    update_any<S, N, true, TRT>(a, sc, slot, fl, cell0);
   else
-    update_any<S, N, false>(a, sc, slot, fl, cell0);
+    update_any<S, N, false, TRT>(a, sc, slot, fl, cell0);
 }
 
 // Workgroup splits that keep at least one full wavefront per workgroup.
@@ -545,18 +593,19 @@ __device__ __forceinline__ int xcd_unit(int b, int n) {
 }
 
 // One workgroup per work unit (PERSIST = false), or a fixed grid of
-// workgroups looping over the units (PERSIST = true).
-template <typename S, int N, bool PERSIST, int SPLIT>
+// workgroups looping over the units (PERSIST = true).  TRT: the TRT
+// collision with a body force instead of SRT.
+template <typename S, int N, bool PERSIST, int SPLIT, bool TRT = false>
 __global__ void __launch_bounds__((Geo<S, N>::T / SPLIT)) sweep_kernel(SweepArgs a) {
   __shared__ SlotCache sc;
   const int units = a.nwork * SPLIT;
   if (!PERSIST) {
     const int b = int(blockIdx.x);
-    sweep_item<S, N, SPLIT>(a, sc, a.xcd ? xcd_unit(b, units) : b);
+    sweep_item<S, N, SPLIT, TRT>(a, sc, a.xcd ? xcd_unit(b, units) : b);
     return;
   }
   for (int w = blockIdx.x; w < units; w += gridDim.x) {
-    sweep_item<S, N, SPLIT>(a, sc, a.xcd ? xcd_unit(w, units) : w);
+    sweep_item<S, N, SPLIT, TRT>(a, sc, a.xcd ? xcd_unit(w, units) : w);
     __syncthreads();
   }
 }
@@ -581,7 +630,8 @@ int sweep_split_t(int n, int requested) {
 
 // Launch of one level substep for storage type S: `split` must be the value
 // sweep_split_t returns, grid >= nwork * split launches one workgroup per
-// work unit, a smaller grid a persistent one.
+// work unit, a smaller grid a persistent one (SRT only: the TRT form always
+// launches one workgroup per work unit).
 template <typename S>
 hipError_t launch_sweep_t(int n, const SweepArgs& a, int grid, int split, hipStream_t stream) {
   auto go = [&](auto nn, auto ss) -> hipError_t {
@@ -590,7 +640,9 @@ hipError_t launch_sweep_t(int n, const SweepArgs& a, int grid, int split, hipStr
       return hipErrorInvalidValue;
     } else {
       constexpr int T = Geo<S, N>::T / SPLIT;
-      if (grid < a.nwork * SPLIT)
+      if (a.trt)
+        hipLaunchKernelGGL((sweep_kernel<S, N, false, SPLIT, true>), dim3(a.nwork * SPLIT), dim3(T), 0, stream, a);
+      else if (grid < a.nwork * SPLIT)
         hipLaunchKernelGGL((sweep_kernel<S, N, true, SPLIT>), dim3(grid), dim3(T), 0, stream, a);
       else
         hipLaunchKernelGGL((sweep_kernel<S, N, false, SPLIT>), dim3(a.nwork * SPLIT), dim3(T), 0, stream, a);

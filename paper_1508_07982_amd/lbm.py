@@ -65,6 +65,7 @@ _SIGNATURES = {
     "lbm_level_stats": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
     "lbm_set_level_omega": [ctypes.c_void_p, ctypes.c_double],
     "lbm_get_level_omega": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
+    "lbm_set_trt_force": [ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p],
     "lbm_init_pdfs": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_step_coarse": [ctypes.c_void_p, ctypes.c_int],
     "lbm_get_moments": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
@@ -250,6 +251,13 @@ class Forest:
     # -- parameters and state --------------------------------------------------
     def set_level_omega(self, omega0: float):
         _check(self._lib.lbm_set_level_omega(self._h, float(omega0)))
+
+    def set_trt_force(self, lambda_eo: float = 0.0, accel=None):
+        """TRT with Lambda_eo = lambda_eo (0: lambda_o = lambda_e) and the
+        level-0 lattice acceleration `accel` (3 values or None); call before
+        init_pdfs.  lambda_eo = 0 without acceleration is SRT."""
+        a = None if accel is None else np.ascontiguousarray(accel, dtype=np.float64).reshape(3)
+        _check(self._lib.lbm_set_trt_force(self._h, float(lambda_eo), _ptr(a) if a is not None else None))
 
     def level_omega(self, level: int) -> float:
         v = ctypes.c_double()
