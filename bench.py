@@ -55,10 +55,14 @@ def measured_traffic(storage: str, level_cells: int, launches_ms: float):
         return None
 
 
-def make_forest(lbm, W, w, storage, stream):
+def make_forest(lbm, W, w, storage, stream, trt=None):
+    """trt: (Lambda_eo, level-0 acceleration) for the TRT collision with a
+    body force, None for SRT."""
     g = lbm.Forest(w.R, w.n, w.max_level, refine=w.refine, storage=storage, stream=stream)
     rho, u = W.initial_field(w, g.leaves())
     g.set_level_omega(w.omega0)
+    if trt is not None:
+        g.set_trt_force(*trt)
     g.init_pdfs(rho, u)
     del rho, u
     return g
@@ -216,6 +220,20 @@ def main():
                               "launch": launch_table(launch64), "mass_drift": abs(M64b - M64a) / M64a}
         g64.close()
         del g64
+        # TRT with Lambda_eo = 3/16 and a body force along x (section 2), FP32
+        gt = make_forest(lbm, W, w, "f32", stream.cuda_stream, trt=(3.0 / 16.0, (1e-6, 0.0, 0.0)))
+        launcht = gt.autotune(1)
+        gt.step_coarse(1)
+        Mta, _ = gt.mass()
+        mst = timed_steps(torch, gt, stream, 5)
+        Mtb, _ = gt.mass()
+        swt, cot = gt.time_launches(1)
+        forms["f32_trt_force_graph"] = {"MLUPS": round(upd / (mst * 1e-3) / 1e6, 1), "ms_per_step": round(mst, 3),
+                                        "lambda_eo": 3.0 / 16.0, "accel0": [1e-6, 0.0, 0.0],
+                                        "per_level": level_table(gt, swt, 4, cot),
+                                        "launch": launch_table(launcht), "mass_drift": abs(Mtb - Mta) / Mta}
+        gt.close()
+        del gt
         forms["batching_slab_sphere"] = batching_form(torch, lbm, W, stream)
         gp = make_forest(lbm, W, w, "f32", stream.cuda_stream)
         gp.set_schedule("per_block")

@@ -197,8 +197,11 @@ int lbm_get_level_launch(const lbm_forest *f, int level, int *persistent, int *o
  * candidate (persistent, order, split) -- one workgroup per work unit with
  * order {0, 1} x split {1, 2, 4}, and persistent grids of {1, 2, 4, 8}
  * workgroups per CU with order {0, 1} -- with lbm_time_sweeps over one
- * warm-up and n_steps >= 1 coarse steps, keeps for every level the
+ * warm-up and n_steps >= 1 coarse steps, in two passes over all candidates
+ * (each candidate keeps its faster pass), keeps for every level the
  * candidate with the smallest mean step time of that level, and applies it.
+ * With TRT (lbm_set_trt_force) a persistent candidate runs one workgroup
+ * per work unit.
  * result[4 * L + {0, 1, 2, 3}] = chosen persistent, order, split and that
  * level's mean time per level step in ms.  The PDF state is saved before
  * and restored after (device memory equal to the forest's PDF storage is

@@ -690,22 +690,26 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
     std::vector<int> bp(nl, 0), bo(nl, 0), bs(nl, 1);
     std::vector<double> ms(2 * nl);
     std::vector<int64_t> cnt(2 * nl);
-    for (int c = 0; c < ncand; ++c) {
-      for (int L = 0; L < nl; ++L) {
-        f->lv[L].persistent = kCand[c][0];
-        f->lv[L].order = kCand[c][1];
-        f->lv[L].split = sweep_split(f->storage, f->n, kCand[c][2]);
-      }
-      if ((rc = lbm_time_sweeps(f, 1, ms.data(), cnt.data()))) return rc;  // warm-up
-      if ((rc = lbm_time_sweeps(f, n_steps, ms.data(), cnt.data()))) return rc;
-      for (int L = 0; L < nl; ++L) {
-        // mean time of one step of level L: its substeps' mean launch durations
-        const double t = ms[2 * L] + (L > 0 ? ms[2 * L + 1] : 0.0);
-        if (f->lv[L].nwork > 0 && t < best[L]) {
-          best[L] = t;
-          bp[L] = kCand[c][0];
-          bo[L] = kCand[c][1];
-          bs[L] = f->lv[L].split;
+    // two passes over the candidates, each candidate keeping its faster
+    // pass: a drift of the clocks during the search then favours no candidate
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int c = 0; c < ncand; ++c) {
+        for (int L = 0; L < nl; ++L) {
+          f->lv[L].persistent = kCand[c][0];
+          f->lv[L].order = kCand[c][1];
+          f->lv[L].split = sweep_split(f->storage, f->n, kCand[c][2]);
+        }
+        if ((rc = lbm_time_sweeps(f, 1, ms.data(), cnt.data()))) return rc;  // warm-up
+        if ((rc = lbm_time_sweeps(f, n_steps, ms.data(), cnt.data()))) return rc;
+        for (int L = 0; L < nl; ++L) {
+          // mean time of one step of level L: its substeps' mean launch durations
+          const double t = ms[2 * L] + (L > 0 ? ms[2 * L + 1] : 0.0);
+          if (f->lv[L].nwork > 0 && t < best[L]) {
+            best[L] = t;
+            bp[L] = kCand[c][0];
+            bo[L] = kCand[c][1];
+            bs[L] = f->lv[L].split;
+          }
         }
       }
     }
