@@ -86,10 +86,10 @@ def test_trt_force_momentum_growth_on_gpu():
     g.close()
 
 
-@pytest.mark.parametrize("storage, tol", [("f32", 1e-5), ("f16", 1e-3)])
-def test_trt_force_storage_forms(storage, tol):
-    say(f"trt+force {storage}")
-    o, g = make_pair(8, storage)
+@pytest.mark.parametrize("storage, n, tol", [("f32", 8, 1e-5), ("f16", 8, 1e-3), ("f32", 4, 1e-5), ("f16", 4, 1e-3)])
+def test_trt_force_storage_forms(storage, n, tol):
+    say(f"trt+force {storage} n={n}")
+    o, g = make_pair(n, storage)
     w = o.level_weights()
     o.step(10)
     g.step_coarse(10)
@@ -124,3 +124,35 @@ def test_trt_off_is_srt_and_refusals():
                 g.set_trt_force(0.1, (np.nan, 0.0, 0.0))
         g.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+def _trt_forest(schedule="graph"):
+    R, n, Lmax, refine = three_level(8)
+    g = lbm.Forest(R, n, Lmax, refine=refine, storage="f32")
+    N = g.num_cells()
+    rng = np.random.default_rng(11)
+    g.set_level_omega(1.7)
+    g.set_trt_force(LAMBDA_EO, A0)
+    g.set_schedule(schedule)
+    g.init_pdfs(1.0 + 0.01 * rng.uniform(-1, 1, N), 0.02 * rng.uniform(-1, 1, (N, 3)))
+    return g
+
+
+def test_trt_schedules_and_autotune_bitwise():
+    """Graph, direct and per-block launches give the same TRT state, and the
+    autotuner leaves it where it was."""
+    say("trt schedules / autotune")
+    outs = {}
+    for schedule in ("graph", "direct", "per_block"):
+        g = _trt_forest(schedule)
+        g.step_coarse(3)
+        outs[schedule] = g.get_pdfs()
+        g.close()
+    assert np.array_equal(outs["graph"], outs["direct"])
+    assert np.array_equal(outs["graph"], outs["per_block"])
+    g = _trt_forest()
+    g.step_coarse(1)
+    g.autotune(n_steps=1)
+    g.step_coarse(2)
+    assert np.array_equal(g.get_pdfs(), outs["graph"])
+    g.close()
