@@ -77,12 +77,12 @@ def run_sweep(storage: str, steps: int):
     g.close()
 
 
-def _finest_tiles():
+def _finest_tiles(storage: str = "f32"):
     sys.path.insert(0, ROOT)
     from paper_1508_07982_amd import lbm
     from paper_1508_07982_amd import workloads as W
     w = W.config_sphere(32, 4)
-    return {L: lbm.plan_level_stats(w.R, w.n, w.max_level, L, refine=w.refine)["work_tiles"]
+    return {L: lbm.plan_level_stats(w.R, w.n, w.max_level, L, refine=w.refine, storage=storage)["work_tiles"]
             for L in range(w.max_level + 1)}
 
 
@@ -154,7 +154,7 @@ def traffic_summary(copy_fetch, copy_write, sweep_fetch, sweep_write, out, comma
         raise RuntimeError("copy kernel not found in the copy profiles")
     fetch_scale = COPY_BYTES / (max(cf) * 1024.0)
     write_scale = COPY_BYTES / (max(cw) * 1024.0)
-    tiles = _finest_tiles()
+    tiles = _finest_tiles(storage)
     Lf = max(tiles)
     sys.path.insert(0, ROOT)
     def finest(path, counter):
