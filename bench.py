@@ -7,14 +7,17 @@ the surface of a central sphere of radius 0.25 refined at every level up to
 level 3 (121.4 M cells in (0, 352, 984, 2368) blocks), D3Q19 SRT with
 omega_0 = 1.9, Taylor-Green amplitude 0.02 plus seeded noise.  One "step" is
 one coarse time step (Algorithm 1 from level 0: sum_L 2^L N_L = 773 M cell
-updates), FP32 PDFs, whole step captured as a HIP graph with the launch
-shape of every level picked by the library's autotuner; inputs are resident
-in HBM before timing starts.
+updates), whole step captured as a HIP graph with the launch shape of every
+level picked by the library's autotuner; inputs are resident in HBM before
+timing starts.
 
-Prints one JSON line: MLUPS across all levels, the roofline of the dominant
-kernel (the finest-level sweep), the FP16-shifted and plain per-block-launch
-forms on the same grid, and the FP64 CPU oracle timed on the host cores on a
-bounded sample of the same workload.
+The headline (`value`) is the FP64 storage form: the paper measures its
+throughput in double precision.  The FP32 and FP16-shifted storage forms,
+each with its own roofline block, the TRT + body-force form, the batching
+grid (slab + sphere, 16^3 blocks) and the plain per-block-launch form follow
+under `forms`; `ceilings` holds the copy and sweep-shape probes measured in
+the same run, and `cpu_baseline` the FP64 oracle timed on the host cores on
+a bounded sample of the same workload (all cores and one core).
 """
 
 from __future__ import annotations
@@ -22,26 +25,31 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
-
-import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 METRIC = "MLUPS across all levels + % of HBM roofline, FP16/FP32 vs plain form"
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "sweep_traffic_sphere_shell_n32.txt")
+BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
-def measured_traffic(storage: str, level_cells: int, launches_ms: float):
+def traffic_file(storage: str) -> str:
+    suffix = "" if storage == "f32" else "_" + storage
+    return os.path.join(HERE, "profiles", f"sweep_traffic_sphere_shell_n32{suffix}.txt")
+
+
+def measured_traffic(storage: str):
     """HBM bytes per finest-level sweep launch from the committed rocprofv3
     counter summary, or None if absent or taken on another kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(storage)
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -81,12 +89,15 @@ def timed_steps(torch, g, stream, steps):
 
 def level_table(g, sweeps, s_bytes, coal=None):
     """Mean launch time and algorithmic GB/s of every (level, substep), and
-    the mean time of each level's coalescence launch."""
+    the mean time of each level's coalescence launch with the algorithmic
+    GB/s of its pairs (8 child reads, the regular source and the write)."""
     out = {f"L{L}s{s}": {"ms": round(m, 4), "launches": c, "cells": g.num_cells(L),
                          "GBps": round(38 * s_bytes * g.num_cells(L) / (m * 1e-3) / 1e9, 1)}
            for (L, s), (m, c) in sorted(sweeps.items())}
     for L, (m, c) in sorted((coal or {}).items()):
-        out[f"L{L}coalesce"] = {"ms": round(m, 4), "launches": c}
+        pairs = g.level_stats(L)["coalesced_pairs"]
+        out[f"L{L}coalesce"] = {"ms": round(m, 4), "launches": c, "pairs": pairs,
+                                "GBps": round(10 * s_bytes * pairs / (m * 1e-3) / 1e9, 1)}
     return out
 
 
@@ -94,6 +105,47 @@ def launch_table(res):
     """Autotuner choice per level: [persistent workgroups per CU (0: one
     per work unit), tile order (1: grouped by XCD), workgroups per tile]."""
     return {f"L{r['level']}": [r["persistent"], r["order"], r["split"]] for r in res}
+
+
+def roofline_block(g, storage, sweeps):
+    """Roofline of the dominant kernel, the finest-level sweep: algorithmic
+    bytes per launch (19 PDFs read and 19 written per interior cell) over
+    its mean launch time from HIP events on the library's stream."""
+    Lf = g.num_levels - 1
+    fin = [sweeps[k] for k in sweeps if k[0] == Lf]
+    fin_ms = sum(m * c for m, c in fin) / sum(c for _, c in fin)
+    nf = g.num_cells(Lf)
+    alg = 38 * BYTES[storage] * nf
+    achieved = alg / (fin_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(storage),
+            "kernel": f"sweep_kernel<{ {'f64': 'double', 'f32': 'float', 'f16': '__half'}[storage]},32> on level {Lf}",
+            "algorithmic_bytes_per_launch": alg, "cells_per_launch": nf, "bytes_per_cell_update": 38 * BYTES[storage],
+            "mean_launch_ms": round(fin_ms, 4)}
+
+
+def storage_form(torch, lbm, W, w, storage, stream, steps, warmup):
+    """MLUPS, roofline and per-level table of one storage form on the
+    benchmark grid (graph schedule, autotuned launch shapes)."""
+    g = make_forest(lbm, W, w, storage, stream.cuda_stream)
+    upd = g.updates_per_coarse_step()
+    launch = g.autotune(1 if storage == "f64" else 2)  # state restored afterwards
+    g.step_coarse(warmup)
+    M0, _ = g.mass()
+    ms = timed_steps(torch, g, stream, steps)
+    M1, _ = g.mass()
+    sweeps, coal = g.time_launches(1 if storage == "f64" else 2)
+    value = upd / (ms * 1e-3) / 1e6
+    roof_mlups = HBM_PEAK_GBS * 1e9 / (38 * BYTES[storage]) / 1e6
+    out = {"MLUPS": round(value, 1), "ms_per_step": round(ms, 4), "steps": steps,
+           "roofline_MLUPS": round(roof_mlups, 1), "frac_of_roofline_MLUPS": round(value / roof_mlups, 4),
+           "roofline": roofline_block(g, storage, sweeps), "per_level": level_table(g, sweeps, BYTES[storage], coal),
+           "launch": launch_table(launch), "mass_drift": abs(M1 - M0) / M0,
+           "cells": g.num_cells(), "updates_per_coarse_step": upd}
+    g.close()
+    del g
+    torch.cuda.synchronize()
+    return out
 
 
 def batching_form(torch, lbm, W, stream):
@@ -114,36 +166,84 @@ def batching_form(torch, lbm, W, stream):
         ms = timed_steps(torch, g, stream, 20 if label != "per_block" else 3)
         out[f"{label}_ms_per_step"] = round(ms, 4)
         out[f"{label}_MLUPS"] = round(g.updates_per_coarse_step() / (ms * 1e-3) / 1e6, 1)
+        if label == "graph_autotuned":
+            sweeps, coal = g.time_launches(3)
+            out["per_level"] = level_table(g, sweeps, 4, coal)
+            busy = sum(m * c for m, c in sweeps.values()) / 3 + sum(m * c for m, c in coal.values()) / 3
+            out["kernel_busy_ms_per_step"] = round(busy, 4)
+            out["algorithmic_GBps"] = round(g.updates_per_coarse_step() * 152 / (ms * 1e-3) / 1e9, 1)
         g.close()
         del g
     return out
 
 
-def cpu_baseline(W, budget_s: float = 12.0):
+def ceilings_now(torch, lbm):
+    """The copy probe and the sweep-shape probe at the finest level's size
+    (FP64 elements, 2368 blocks of 32^3 cells), measured in this run."""
+    from paper_1508_07982_amd import profiling
+    rows = profiling.ceilings(blocks=2368, n=32, iters=5)
+    best = {}
+    for r in rows:
+        key = "copy" if r["probe"] == "copy" else f"sweep_shape_{r['elem_bytes']}B"
+        if r["GBps"] > best.get(key, {"GBps": 0})["GBps"]:
+            best[key] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+    return best
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(W, budget_s: float = 10.0):
     """The FP64 oracle on the same sphere-shell geometry with 8^3-cell
     blocks (1/64 of the cells), timed over as many coarse steps as fit in
-    about `budget_s` seconds (two untimed steps estimate the rate)."""
+    about `budget_s` seconds (one untimed step estimates the rate), first on
+    every host core the process may use, then on one core."""
     from oracle import Forest as OForest, RefinedOracle
+    from oracle.refined import set_threads
     w = W.config_sphere(8, 4)
     f = OForest.build(w.R, w.n, w.max_level, w.refine)
     o = RefinedOracle(f, w.omega0)
     rho, u = W.initial_field(w, f.canonical_leaves())
     o.init_pdfs(rho, u)
-    t = time.perf_counter()
-    o.step(2)
-    per_step = (time.perf_counter() - t) / 2
-    budget_steps = int(min(200, max(2, budget_s / max(per_step, 1e-3))))
-    t = time.perf_counter()
-    o.step(budget_steps)
-    dt = time.perf_counter() - t
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    upd = o.updates_per_coarse_step()
+
+    def run(threads):
+        prev = set_threads(threads)
+        try:
+            t = time.perf_counter()
+            o.step(1)
+            per_step = time.perf_counter() - t
+            steps = int(min(200, max(1, budget_s / max(per_step, 1e-3))))
+            t = time.perf_counter()
+            o.step(steps)
+            dt = time.perf_counter() - t
+        finally:
+            set_threads(prev)
+        return upd * steps / dt / 1e6, steps, dt
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", "0")) or cores)
+    v_all, s_all, t_all = run(cores)
+    v_one, s_one, t_one = run(1)
     return {
-        "value": round(o.updates_per_coarse_step() * budget_steps / dt / 1e6, 3),
+        "value": round(v_all, 3),
         "unit": "MLUPS",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"FP64 oracle, sphere-shell geometry with 8^3-cell blocks ({o.total_cells()} cells, "
-                  f"1/64 of the benchmark grid), {budget_steps} coarse steps, {dt:.1f} s",
+        "sample": f"FP64 oracle (gcc -O3, OpenMP), sphere-shell geometry with 8^3-cell blocks "
+                  f"({o.total_cells()} cells, 1/64 of the benchmark grid), {s_all} coarse steps in {t_all:.1f} s "
+                  f"on {cores} threads",
+        "single_core": {"value": round(v_one, 3), "unit": "MLUPS", "cores": 1,
+                        "sample": f"the same, {s_one} coarse steps in {t_one:.1f} s on 1 thread"},
+        "cpu_model": cpu_model(),
     }
 
 
@@ -152,8 +252,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-forms", action="store_true", help="skip the FP16, FP64 and per-block comparison runs")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the FP32/FP16, TRT, batching and per-block comparison runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the refined grid lives in one GPU's HBM and the library has no "
@@ -166,60 +268,14 @@ def main():
 
     stream = torch.cuda.Stream()
     w = W.config_sphere(32, 4)
-    g = make_forest(lbm, W, w, "f32", stream.cuda_stream)
-    upd = g.updates_per_coarse_step()
-    cells = g.num_cells()
-    launch = g.autotune(2)  # per-level launch shape, state restored afterwards
-    g.step_coarse(args.warmup)
-    M0, _ = g.mass()
-    ms = timed_steps(torch, g, stream, args.steps)
-    M1, _ = g.mass()
-    value = upd / (ms * 1e-3) / 1e6
+    head = storage_form(torch, lbm, W, w, "f64", stream, args.steps, args.warmup)
+    print(f"f64: {head['MLUPS']} MLUPS", file=sys.stderr, flush=True)
 
-    # dominant kernel: the finest-level sweep (77.6 M cells, 8 launches per step)
-    sweeps, coal = g.time_launches(2)
-    Lf = g.num_levels - 1
-    fin = [sweeps[k] for k in sweeps if k[0] == Lf]
-    fin_ms = sum(m * c for m, c in fin) / sum(c for _, c in fin)
-    s_bytes = lbm.STORAGE_BYTES["f32"]
-    nf = g.num_cells(Lf)
-    alg_bytes = 38 * s_bytes * nf          # 19 PDFs read + 19 written per interior cell
-    achieved = alg_bytes / (fin_ms * 1e-3) / 1e9
-    traffic = measured_traffic("f32", nf, fin_ms)
-    per_level = level_table(g, sweeps, s_bytes, coal)
-    g.close()
-    del g
-    torch.cuda.synchronize()
-
-    forms = {"f32_graph": {"MLUPS": round(value, 1), "ms_per_step": round(ms, 3),
-                           "roofline_MLUPS": round(HBM_PEAK_GBS * 1e9 / (38 * 4) / 1e6, 1)}}
+    forms = {}
     if not args.no_forms:
-        g16 = make_forest(lbm, W, w, "f16", stream.cuda_stream)
-        launch16 = g16.autotune(2)
-        g16.step_coarse(2)
-        M16a, _ = g16.mass()
-        ms16 = timed_steps(torch, g16, stream, max(3, args.steps // 2))
-        M16b, _ = g16.mass()
-        sw16, co16 = g16.time_launches(2)
-        forms["f16_graph"] = {"MLUPS": round(upd / (ms16 * 1e-3) / 1e6, 1), "ms_per_step": round(ms16, 3),
-                              "roofline_MLUPS": round(HBM_PEAK_GBS * 1e9 / (38 * 2) / 1e6, 1),
-                              "per_level": level_table(g16, sw16, 2, co16),
-                              "launch": launch_table(launch16), "mass_drift": abs(M16b - M16a) / M16a}
-        g16.close()
-        del g16
-        g64 = make_forest(lbm, W, w, "f64", stream.cuda_stream)
-        launch64 = g64.autotune(1)
-        g64.step_coarse(1)
-        M64a, _ = g64.mass()
-        ms64 = timed_steps(torch, g64, stream, 3)
-        M64b, _ = g64.mass()
-        sw64, co64 = g64.time_launches(1)
-        forms["f64_graph"] = {"MLUPS": round(upd / (ms64 * 1e-3) / 1e6, 1), "ms_per_step": round(ms64, 3),
-                              "roofline_MLUPS": round(HBM_PEAK_GBS * 1e9 / (38 * 8) / 1e6, 1),
-                              "per_level": level_table(g64, sw64, 8, co64),
-                              "launch": launch_table(launch64), "mass_drift": abs(M64b - M64a) / M64a}
-        g64.close()
-        del g64
+        for storage in ("f32", "f16"):
+            forms[f"{storage}_graph"] = storage_form(torch, lbm, W, w, storage, stream, args.steps, args.warmup)
+            print(f"{storage}: {forms[storage + '_graph']['MLUPS']} MLUPS", file=sys.stderr, flush=True)
         # TRT with Lambda_eo = 3/16 and a body force along x (section 2), FP32
         gt = make_forest(lbm, W, w, "f32", stream.cuda_stream, trt=(3.0 / 16.0, (1e-6, 0.0, 0.0)))
         launcht = gt.autotune(1)
@@ -228,9 +284,9 @@ def main():
         mst = timed_steps(torch, gt, stream, 5)
         Mtb, _ = gt.mass()
         swt, cot = gt.time_launches(1)
-        forms["f32_trt_force_graph"] = {"MLUPS": round(upd / (mst * 1e-3) / 1e6, 1), "ms_per_step": round(mst, 3),
-                                        "lambda_eo": 3.0 / 16.0, "accel0": [1e-6, 0.0, 0.0],
-                                        "per_level": level_table(gt, swt, 4, cot),
+        forms["f32_trt_force_graph"] = {"MLUPS": round(head["updates_per_coarse_step"] / (mst * 1e-3) / 1e6, 1),
+                                        "ms_per_step": round(mst, 3), "lambda_eo": 3.0 / 16.0,
+                                        "accel0": [1e-6, 0.0, 0.0], "per_level": level_table(gt, swt, 4, cot),
                                         "launch": launch_table(launcht), "mass_drift": abs(Mtb - Mta) / Mta}
         gt.close()
         del gt
@@ -239,49 +295,46 @@ def main():
         gp.set_schedule("per_block")
         gp.step_coarse(1)
         msp = timed_steps(torch, gp, stream, 2)
-        forms["f32_per_block_launch"] = {"MLUPS": round(upd / (msp * 1e-3) / 1e6, 1), "ms_per_step": round(msp, 3)}
+        forms["f32_per_block_launch"] = {"MLUPS": round(head["updates_per_coarse_step"] / (msp * 1e-3) / 1e6, 1),
+                                         "ms_per_step": round(msp, 3)}
         gp.close()
         del gp
         torch.cuda.synchronize()
 
     out = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": head["MLUPS"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
             "workload": w.name,
-            "description": w.description,
-            "cells": cells,
-            "levels": [lv for lv in range(Lf + 1)],
-            "updates_per_coarse_step": upd,
+            "description": w.description + " (level 0 holds no leaves: the 2:1 balance splits every root)",
+            "cells": head["cells"],
+            "blocks_per_level": [lbm.plan_level_stats(w.R, w.n, w.max_level, L, refine=w.refine)["blocks"]
+                                 for L in range(w.max_level + 1)],
+            "updates_per_coarse_step": head["updates_per_coarse_step"],
             "omega0": w.omega0,
+            "storage": "f64 (PDFs stored as f - w in FP64, FP64 arithmetic)",
             "schedule": "hipGraph of the whole coarse step",
-            "launch": launch_table(launch),
-            "mass_drift": abs(M1 - M0) / M0,
+            "launch": head["launch"],
+            "mass_drift": head["mass_drift"],
+            "roofline_MLUPS": head["roofline_MLUPS"],
+            "frac_of_roofline_MLUPS": head["frac_of_roofline_MLUPS"],
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "kernel": f"sweep_kernel<float,32> on level {Lf}",
-            "algorithmic_bytes_per_launch": alg_bytes,
-            "mean_launch_ms": round(fin_ms, 4),
-        },
-        "per_level": per_level,
+        "roofline": head["roofline"],
+        "per_level": head["per_level"],
         "forms": forms,
     }
+    if not args.no_ceilings:
+        out["ceilings"] = ceilings_now(torch, lbm)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)

@@ -141,13 +141,19 @@ int lbm_get_level_omega(const lbm_forest *f, int level, double *omega);
  * accel0[3] (host, may be NULL for none) is the lattice acceleration a_0* of
  * level 0; level L uses a_0* / 2^L (eq. force_scaling) and adds
  * F_a = 3 w_a e_a . a_L after each collision, with u in f^eq the plain sum
- * e f.  lambda_eo == 0 with no acceleration restores SRT.  Call before
- * lbm_init_pdfs (the stored state is post-collision: lbm_init_pdfs adds the
- * force term of one collision), and lbm_get_moments then reports
- * u = sum e f / rho0 + a_L / 2 of the pre-collision state.  lbm_regrid
- * refuses a forest with TRT or a force (LBM_E_STATE).
+ * e f.  lambda_eo == 0 with no acceleration restores SRT.  The acceleration
+ * is set before lbm_init_pdfs: the stored state is post-collision, and
+ * lbm_init_pdfs (and lbm_set_pdfs, whose input is taken as such a state)
+ * includes the force term of one collision; once PDFs are set, a call with a
+ * different acceleration returns LBM_E_STATE (lambda_eo alone may change).
+ * lbm_get_moments then reports u = sum e f / rho0 + a_L / 2 of the
+ * pre-collision state, and lbm_mass the momentum of the stored
+ * (post-collision) state, which holds a_L / 2 more per unit mass than the
+ * pre-collision one.  lbm_regrid refuses a forest with TRT or a force
+ * (LBM_E_STATE).
  * Errors: LBM_E_INVALID (null handle, lambda_eo < 0 or not finite, a
- * non-finite acceleration). */
+ * non-finite acceleration), LBM_E_STATE (acceleration changed after the
+ * PDFs were set). */
 int lbm_set_trt_force(lbm_forest *f, double lambda_eo, const double accel0[3]);
 
 /* f = f^eq(rho, u) (eq. fequ) on every interior cell.  rho[N], u[N][3],
@@ -159,14 +165,21 @@ int lbm_init_pdfs(lbm_forest *f, const double *rho, const double *u);
 int lbm_step_coarse(lbm_forest *f, int n_steps);
 
 /* Density and velocity of every interior cell (eq. fvelocity read as
- * rho = sum f, u = sum e f / rho0), host FP64 in canonical order.
+ * rho = sum f, u = sum e f / rho0), host FP64 in canonical order.  With a
+ * body force (lbm_set_trt_force) the stored post-collision state carries the
+ * force term F_a = 3 w_a e_a . a_L, and u = sum e f / rho0 - a_L / 2 of it,
+ * which is the paper's velocity sum e f / rho0 + a_L / 2 of the
+ * pre-collision state (section 2, external forces).
  * Synchronizes the stream. */
 int lbm_get_moments(lbm_forest *f, double *rho, double *u);
 
 /* Volume-weighted mass and momentum, M = sum_L 8^-L sum_{cells} sum_a f_a
- * and J = sum_L 8^-L sum sum e_a f_a, accumulated in FP64 on the device
- * (cell volume (dx_L / dx_0)^3).  LBM_E_NONFINITE if NaN or Inf appears.
- * Synchronizes the stream. */
+ * and J = sum_L 8^-L sum sum e_a f_a, accumulated in FP64 on the device.
+ * The weight of a level-L cell is its volume (dx_L / dx_0)^3 = 8^-L in
+ * units of a level-0 cell, as in the volume-weighted error norms of the
+ * validation (section 5.1); the volume-based scheme conserves M across
+ * levels (section 4.4).  The sum covers the stored (post-collision) state.
+ * LBM_E_NONFINITE if NaN or Inf appears.  Synchronizes the stream. */
 int lbm_mass(lbm_forest *f, double *mass, double momentum[3]);
 
 /* Schedule of lbm_step_coarse: LBM_SCHED_GRAPH (default), _DIRECT or

@@ -52,6 +52,8 @@ def _load():
                                         ctypes.c_void_p]
         lib.orc_lattice.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_stream_calls.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = ctypes.c_int
         if lib.orc_sizeof_level() != ctypes.sizeof(_Level):
             raise RuntimeError("oracle struct layout mismatch")
         _lib = lib
@@ -60,6 +62,12 @@ def _load():
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+
+
+def set_threads(n: int) -> int:
+    """Host threads of the oracle's loops (n <= 0 leaves them); returns the
+    previous maximum."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def lattice():

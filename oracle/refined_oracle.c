@@ -28,6 +28,7 @@
  * (section 2.2: periodic boundaries are handled by the communication).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -220,3 +221,11 @@ void orc_coarse_steps(orc_level *levels, int num_levels, int steps) {
 }
 
 int orc_sizeof_level(void) { return (int)sizeof(orc_level); }
+
+/* threads of the OpenMP loops above (for timing the oracle on a given number
+   of host cores); returns the previous maximum */
+int orc_set_threads(int n) {
+  const int prev = omp_get_max_threads();
+  if (n > 0) omp_set_num_threads(n);
+  return prev;
+}

@@ -219,7 +219,8 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   a.par = parent_cur;
   a.fine0 = fine0;
   a.fine1 = fine1;
-  a.work = d.work;
+  a.work = nullptr;  // every tile of the level, in canonical order
+  a.work0 = 0;
   a.nwork = d.nwork;
   a.xcd = d.order;
   a.substep = substep;
@@ -293,7 +294,8 @@ int run_ops(lbm_forest* f, const std::vector<Op>& ops, bool per_block) {
       const LevelDev& d = f->lv[op.level];
       for (int s = 0; s < d.nblocks; ++s) {
         SweepArgs a = op.args;
-        a.work = d.work + size_t(s) * d.tiles_per_block;
+        a.work = nullptr;
+        a.work0 = s * d.tiles_per_block;
         a.nwork = d.tiles_per_block;
         HIP_TRY(launch_sweep(f->storage, f->n, a, a.nwork, 1, f->stream));
       }
@@ -561,6 +563,10 @@ int lbm_set_trt_force(lbm_forest* f, double lambda_eo, const double* accel0) {
     if (!std::isfinite(accel0[d])) return fail(LBM_E_INVALID, "acceleration must be finite");
     a[d] = accel0[d];
   }
+  // the stored state is post-collision and holds the force term of one
+  // collision: a new acceleration would leave it inconsistent
+  if (f->state_set && (a[0] != f->accel0[0] || a[1] != f->accel0[1] || a[2] != f->accel0[2]))
+    return fail(LBM_E_STATE, "the acceleration must be set before lbm_init_pdfs");
   f->lambda_eo = lambda_eo;
   for (int d = 0; d < 3; ++d) f->accel0[d] = a[d];
   f->trt = lambda_eo > 0.0 || a[0] != 0.0 || a[1] != 0.0 || a[2] != 0.0;
@@ -606,6 +612,7 @@ int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
     int rc2 = refresh_faces(f);
     if (rc2) return rc2;
     HIP_TRY(hipStreamSynchronize(f->stream));
+    f->state_set = true;
     return LBM_OK;
   };
   rc = body();
@@ -1089,6 +1096,7 @@ int lbm_set_pdfs(lbm_forest* f, const double* h) {
       HIP_TRY(hipMemcpyAsync(d, h + 19 * off, v.ncells * 19 * sizeof(double), hipMemcpyHostToDevice, f->stream));
       HIP_TRY(launch_set_pdfs(f->storage, f->n, current_buffer_mut(f, int(L)), d, v.ncells, f->stream));
       f->steps_since_state = 0;
+      f->state_set = true;
       HIP_TRY(launch_face_copy(f->storage, f->n, current_buffer(f, int(L)), v.xface[f->rot[L]], v.nblocks,
                                f->stream));
       HIP_TRY(hipStreamSynchronize(f->stream));

@@ -5,11 +5,11 @@
 // and corner neighbours.  Section 4: every block holds n^3 cells.
 //
 // Device-side view of one level L: slots [0, nblocks) are the level-L leaves
-// in canonical (Morton) order; a level buffer is direction-major,
-// [direction][slot][cell].  Nothing is stored for the fine ghost layers: the
+// in canonical (Morton) order; a level buffer is block-major,
+// [slot][direction][cell].  Nothing is stored for the fine ghost layers: the
 // two streamed halo layers of section 4 are reconstructed on the fly from
 // the level's state at the start of the parent step and from the parent
-// level (see kernels.hip).
+// level (coarse_source in sweep.hpp, coalesce_kernel in kernels.hip).
 #pragma once
 
 #include <cstdint>

@@ -18,7 +18,8 @@ struct SweepArgs {
   const void* par;            // level-(L-1) post-collision state (explosion source)
   const void* fine0;          // level-(L+1) state at the start of its last parent step
   const void* fine1;          // level-(L+1) state after the first of its two substeps
-  const int32_t* work;        // work tiles: slot * tiles_per_block + tile
+  const int32_t* work;        // work tiles (slot * tiles_per_block + tile), or null: tiles work0 + [0, nwork)
+  int32_t work0;
   int32_t nwork;
   int32_t xcd;                // 1: work units grouped by XCD (see xcd_unit in the sweep)
   int32_t substep;            // 1 or 2

@@ -73,6 +73,7 @@ struct lbm_forest {
   std::vector<int> rot;       // per level: buffer holding the current state
   std::vector<int> rot_prev;  // the same at the start of the last coarse step
   int64_t steps_since_state = 0;  // coarse steps since the state was set (init, set_pdfs, regrid)
+  bool state_set = false;         // PDFs written by lbm_init_pdfs or lbm_set_pdfs
   int max_level = 0;              // deepest level a regrid may create
   double omega0 = 0.0;
   bool trt = false;               // TRT collision with a body force (lbm_set_trt_force)

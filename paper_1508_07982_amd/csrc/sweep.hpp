@@ -2,20 +2,24 @@
 // storage form in sweep_f64.hip, sweep_f32.hip and sweep_f16.hip).
 //
 // One launch of `sweep_kernel` performs one substep of one level L
-// (section 4, Algorithm 1, in post-collision form):
-//
-//   for every live cell x of level L (interior cells of the level-L blocks
-//   and the halo cells of its ghost blocks) and every direction a:
-//     - (x, a) in the coalescence set  -> mean of the 8 children of x in
-//       level L+1 after its two substeps (eq. ftoc);
-//     - source x - e_a inside a level-L block -> that block's value;
-//     - source in a ghost block (coarser region):
+// (section 4, Algorithm 1, in post-collision form).  Its work list holds the
+// level-L blocks only; nothing is stored or computed for ghost cells.  For
+// every interior cell x of level L and every direction a the pulled value is
+//   - (x, a) in the coalescence set (x - e_a, or for an edge direction one
+//     of its axis projections, lies in region(L+1)) -> the mean of the 8
+//     children of x after the finer level's two substeps (eq. ftoc), computed
+//     by the coalescence launch before this sweep;
+//   - source x - e_a inside a level-L block -> that block's value;
+//   - source in the coarser region (a virtual level-L cell of a ghost
+//     layer), reconstructed by a back-trace instead of a stored halo:
 //         substep 1: the parent's post-collision value (explosion eq. ctof,
-//                    done as a gather, nothing is written);
-//         substep 2: the ghost block's halo value from substep 1 if the
-//                    source is a halo cell, else the parent's value;
-//   interior cells are then collided (SRT, eq. fequ) and written; halo cells
-//   are written uncollided (ghost layers are streamed, never collided).
+//                    done as a gather);
+//         substep 2: the value that the first substep streamed into the
+//                    ghost cell x - e_a, i.e. the level's own state at t at
+//                    x - 2 e_a if that is a level-L cell, else the parent's
+//                    value (ghost layers stream, never collide).
+// Every interior cell is then collided (SRT, eq. fequ; or TRT with a body
+// force) and written.
 //
 // The stored state is post-collision: the collision that Algorithm 1 does at
 // the start of the next step is done at the end of this one.  Moments and
@@ -39,12 +43,52 @@
 namespace lbm {
 namespace dev {
 
-// Per-workgroup copy of the slot's neighbour table and, for a slot with
-// finer neighbours, its row in the coalesced-value buffers.
+// The slot's neighbour table and, for a slot with finer neighbours, its row
+// in the coalesced-value buffers.  Every lane of a workgroup sweeps the same
+// slot, so the table is loaded once per lane into scalar registers (no LDS
+// copy and no barrier before the first PDF load) and indexed only with
+// compile-time offsets (see pick).
 struct SlotCache {
   int32_t nbr[27];
   int32_t fine_row;
 };
+
+template <int X, int Y, int Z>
+__device__ __forceinline__ int32_t nbr_at(const SlotCache& sc) {
+  return sc.nbr[13 + X + 3 * Y + 9 * Z];
+}
+template <int DX, int Y, int Z>
+__device__ __forceinline__ int32_t pick_x(const SlotCache& sc, bool bx) {
+  if constexpr (DX == 0)
+    return nbr_at<0, Y, Z>(sc);
+  else
+    return bx ? nbr_at<DX, Y, Z>(sc) : nbr_at<0, Y, Z>(sc);
+}
+template <int DX, int DY, int Z>
+__device__ __forceinline__ int32_t pick_xy(const SlotCache& sc, bool bx, bool by) {
+  if constexpr (DY == 0)
+    return pick_x<DX, 0, Z>(sc, bx);
+  else
+    return by ? pick_x<DX, DY, Z>(sc, bx) : pick_x<DX, 0, Z>(sc, bx);
+}
+// Table entry of the neighbour offset whose components are DX, DY, DZ
+// where bx, by, bz are set and 0 elsewhere.  A shift by -e_a (or -2 e_a)
+// leaves the block only through the faces the direction points away from,
+// so every lookup of direction a has this form with (DX, DY, DZ) = -e_a:
+// at most 8 candidates, selected per lane from the scalar table.
+template <int DX, int DY, int DZ>
+__device__ __forceinline__ int32_t pick(const SlotCache& sc, bool bx, bool by, bool bz) {
+  if constexpr (DZ == 0)
+    return pick_xy<DX, DY, 0>(sc, bx, by);
+  else
+    return bz ? pick_xy<DX, DY, DZ>(sc, bx, by) : pick_xy<DX, DY, 0>(sc, bx, by);
+}
+
+// Whether a local coordinate lies outside [0, N).
+template <int N>
+__device__ __forceinline__ bool outside(int c) {
+  return c < 0 || c >= N;
+}
 
 // Neighbour offset (-1, 0, +1) of a local coordinate after a shift.
 template <int N>
@@ -79,14 +123,14 @@ __device__ __forceinline__ const S* coarse_source(const SweepArgs& a, const Slot
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
   const S* dummy = static_cast<const S*>(a.cur);
   const int sx = i - EX, sy = j - EY, sz = k - EZ;
-  const int code = sc.nbr[13 + side<N>(sx) + 3 * side<N>(sy) + 9 * side<N>(sz)];
+  const int code = pick<-EX, -EY, -EZ>(sc, outside<N>(sx), outside<N>(sy), outside<N>(sz));
   if (code > kNbrCoarse0) {  // not a coarse region: never expected here
     atomicOr(a.err, kErrNoSource);
     return dummy;
   }
   if (a.substep == 1) return parent_ptr<S, N, A>(a, code, sx & (N - 1), sy & (N - 1), sz & (N - 1));
   const int zx = sx - EX, zy = sy - EY, zz = sz - EZ;
-  const int cz = sc.nbr[13 + side<N>(zx) + 3 * side<N>(zy) + 9 * side<N>(zz)];
+  const int cz = pick<-EX, -EY, -EZ>(sc, outside<N>(zx), outside<N>(zy), outside<N>(zz));
   if (cz >= 0)
     return static_cast<const S*>(a.prev) +
            pdf_index<N>(A, uint32_t(cz), uint32_t((zx & (N - 1)) + N * ((zy & (N - 1)) + N * (zz & (N - 1)))));
@@ -130,18 +174,16 @@ __device__ __forceinline__ void issue_dir(const SweepArgs& a, const SlotCache& s
   constexpr int W = Geo<S, N>::W;
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
   const int sy = j - EY, sz = k - EZ;
-  const int oy = EY == 0 ? 0 : side<N>(sy);
-  const int oz = EZ == 0 ? 0 : side<N>(sz);
+  const bool by = outside<N>(sy), bz = outside<N>(sz);
   const uint32_t row = uint32_t(N * ((sy & (N - 1)) + N * (sz & (N - 1))));
-  const int dmain = 13 + 3 * oy + 9 * oz;
-  const int nbm = sc.nbr[dmain];
+  const int nbm = pick<0, -EY, -EZ>(sc, false, by, bz);
   if (!SIMPLE) odd |= uint32_t(nbm < 0);
   const S* __restrict__ base = static_cast<const S*>(a.cur);
   const uint64_t bm = pdf_index<N>(A, uint32_t(SIMPLE || nbm >= 0 ? nbm : slot), row + uint32_t(i0));
   Vec<S>::load(base + bm, h[A]);
   if constexpr (EX != 0) {
     const bool at_end = EX == 1 ? i0 == 0 : i0 == N - W;
-    const int nbx = sc.nbr[dmain - EX];
+    const int nbx = pick<-EX, -EY, -EZ>(sc, true, by, bz);
     if (!SIMPLE) odd |= uint32_t(at_end && nbx < 0);
     // the end element of the x neighbour's source row, cell N - 1 (EX = 1)
     // or 0 (EX = -1): a value leaving that block through its x face
@@ -194,7 +236,7 @@ __device__ __forceinline__ void pull_all(const SweepArgs& a, const SlotCache& sc
 
 // The slot's neighbour table as two 27-bit masks: neighbours that are not
 // level-L blocks (bit d for table entry d < 0) and finer neighbours
-// (entry d == kNbrFine).  Read once per lane from LDS; the per-direction
+// (entry d == kNbrFine), computed from the scalar table; the per-direction
 // tests below are then bit tests.
 struct NbrMasks {
   uint32_t other;
@@ -421,11 +463,9 @@ __device__ __forceinline__ void issue_dir_h8(const SweepArgs& a, const SlotCache
                                              uint32_t (*q)[4], uint32_t* edge, uint32_t& odd) {
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
   const int sy = j - EY, sz = k - EZ;
-  const int oy = EY == 0 ? 0 : side<N>(sy);
-  const int oz = EZ == 0 ? 0 : side<N>(sz);
+  const bool by = outside<N>(sy), bz = outside<N>(sz);
   const uint32_t row = uint32_t(N * ((sy & (N - 1)) + N * (sz & (N - 1))));
-  const int dmain = 13 + 3 * oy + 9 * oz;
-  const int nbm = sc.nbr[dmain];
+  const int nbm = pick<0, -EY, -EZ>(sc, false, by, bz);
   if (!SIMPLE) odd |= uint32_t(nbm < 0);
   const uint16_t* __restrict__ base = static_cast<const uint16_t*>(a.cur);
   const int bms = SIMPLE || nbm >= 0 ? nbm : slot;
@@ -433,7 +473,7 @@ __device__ __forceinline__ void issue_dir_h8(const SweepArgs& a, const SlotCache
   q[A][0] = v.x, q[A][1] = v.y, q[A][2] = v.z, q[A][3] = v.w;
   if constexpr (EX != 0) {
     const bool at_end = EX == 1 ? i0 == 0 : i0 == N - 8;
-    const int nbx = sc.nbr[dmain - EX];
+    const int nbx = pick<-EX, -EY, -EZ>(sc, true, by, bz);
     if (!SIMPLE) odd |= uint32_t(at_end && nbx < 0);
     const int eb = SIMPLE || nbx >= 0 ? nbx : slot;  // as in issue_dir
     edge[xdir_index(A)] = static_cast<const uint16_t*>(a.face_cur)[xface_index<N, A>(uint32_t(eb), row / N)];
@@ -557,19 +597,21 @@ __device__ __forceinline__ void update_any(const SweepArgs& a, const SlotCache& 
 // SPLIT consecutive runs of whole rows, one per workgroup of T / SPLIT
 // lanes).
 template <typename S, int N, int SPLIT, bool TRT>
-__device__ __forceinline__ void sweep_item(const SweepArgs& a, SlotCache& sc, int w) {
+__device__ __forceinline__ void sweep_item(const SweepArgs& a, int w) {
   constexpr int W = Geo<S, N>::W, CELLS = Geo<S, N>::CELLS, TPB = Geo<S, N>::TPB;
-  const int item = a.work[w / SPLIT];
-  const int slot = item / TPB;
+  const int item = a.work ? a.work[w / SPLIT] : a.work0 + w / SPLIT;
+  const int slot = __builtin_amdgcn_readfirstlane(item / TPB);
   const int cell0 = (item - slot * TPB) * CELLS + (w % SPLIT) * (CELLS / SPLIT) + int(threadIdx.x) * W;
-  const uint32_t fl = a.flags[slot];
-  for (int q = threadIdx.x; q < 27; q += blockDim.x) sc.nbr[q] = a.nbr[slot * 27 + q];
-  if (threadIdx.x == 0) {
-    const int row = fl & kHasFine ? a.fine_index[slot] : 0;
-    if (row < 0) atomicOr(a.err, kErrNoChild);
-    sc.fine_row = row < 0 ? 0 : row;
-  }
-  __syncthreads();
+  // the slot's table, flags and fine row: loads of uniform addresses that
+  // do not depend on each other, all in flight together
+  SlotCache sc;
+  const int32_t* nb = a.nbr + int64_t(slot) * 27;
+#pragma unroll
+  for (int q = 0; q < 27; ++q) sc.nbr[q] = __builtin_amdgcn_readfirstlane(nb[q]);
+  const uint32_t fl = uint32_t(__builtin_amdgcn_readfirstlane(int(a.flags[slot])));
+  const int row = __builtin_amdgcn_readfirstlane(a.fine_index[slot]);
+  if ((fl & kHasFine) && row < 0 && threadIdx.x == 0) atomicOr(a.err, kErrNoChild);
+  sc.fine_row = (fl & kHasFine) && row >= 0 ? row : 0;
   if (fl & kAllSameLevel)
     update_any<S, N, true, TRT>(a, sc, slot, fl, cell0);
   else
@@ -597,17 +639,13 @@ __device__ __forceinline__ int xcd_unit(int b, int n) {
 // collision with a body force instead of SRT.
 template <typename S, int N, bool PERSIST, int SPLIT, bool TRT = false>
 __global__ void __launch_bounds__((Geo<S, N>::T / SPLIT)) sweep_kernel(SweepArgs a) {
-  __shared__ SlotCache sc;
   const int units = a.nwork * SPLIT;
   if (!PERSIST) {
     const int b = int(blockIdx.x);
-    sweep_item<S, N, SPLIT, TRT>(a, sc, a.xcd ? xcd_unit(b, units) : b);
+    sweep_item<S, N, SPLIT, TRT>(a, a.xcd ? xcd_unit(b, units) : b);
     return;
   }
-  for (int w = blockIdx.x; w < units; w += gridDim.x) {
-    sweep_item<S, N, SPLIT, TRT>(a, sc, a.xcd ? xcd_unit(w, units) : w);
-    __syncthreads();
-  }
+  for (int w = blockIdx.x; w < units; w += gridDim.x) sweep_item<S, N, SPLIT, TRT>(a, a.xcd ? xcd_unit(w, units) : w);
 }
 
 // Largest split <= `requested` (1, 2 or 4) valid for storage S and n.

@@ -102,6 +102,10 @@ _SIGNATURES = {
     "lbm_lattice": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_build_leaves": [ctypes.POINTER(ForestDesc), ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
     "lbm_plan_level_stats": [ctypes.POINTER(ForestDesc), ctypes.c_int, ctypes.c_void_p],
+    "lbm_probe_copy": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                       ctypes.POINTER(ctypes.c_double)],
+    "lbm_probe_streams": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)],
 }
 
 
@@ -469,3 +473,29 @@ class MLP:
         _check(self._lib.lbm_mlp_train(self._h, _ptr(X), _ptr(t), len(X), int(epochs), int(batch), float(lr),
                                        int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(losses)))
         return losses[:epochs]
+
+
+# ---- bandwidth probes (lbm_probe.h) ------------------------------------------
+
+def probe_copy(dst_ptr: int, src_ptr: int, nbytes: int, iters: int = 5, nontemporal: bool = True,
+               stream: int = 0) -> float:
+    """Mean time in ms of a 16-byte-vector device copy of nbytes between two
+    caller-owned device buffers (raw device addresses)."""
+    lib = load_library()
+    ms = ctypes.c_double()
+    _check(lib.lbm_probe_copy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), int(nbytes), int(iters),
+                              int(bool(nontemporal)), ctypes.c_void_p(stream or None), ctypes.byref(ms)))
+    return ms.value
+
+
+def probe_streams(dst_ptr: int, src_ptr: int, nblocks: int, n: int, elem_bytes: int, lanes: int = 256,
+                  xcd: bool = False, iters: int = 5, stream: int = 0) -> float:
+    """Mean launch time in ms of the sweep's access shape without arithmetic
+    over nblocks blocks of 19 rows of n^3 elements (both buffers must hold
+    nblocks * 19 * n^3 * elem_bytes bytes)."""
+    lib = load_library()
+    ms = ctypes.c_double()
+    _check(lib.lbm_probe_streams(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), int(nblocks), int(n),
+                                 int(elem_bytes), int(lanes), int(bool(xcd)), int(iters),
+                                 ctypes.c_void_p(stream or None), ctypes.byref(ms)))
+    return ms.value

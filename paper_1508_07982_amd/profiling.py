@@ -1,17 +1,21 @@
 """Profiling helpers: workloads to run under rocprofv3 and summaries of its output.
 
     python -m paper_1508_07982_amd.profiling copy                 # 1 GiB device copy x 3 (counter scale)
-    python -m paper_1508_07982_amd.profiling sweep [--storage f32] [--steps 2]
+    python -m paper_1508_07982_amd.profiling ceiling OUT.txt       # copy and sweep-shape probes
+    python -m paper_1508_07982_amd.profiling sweep [--storage f32] [--workload sphere|slab] [--steps 2]
     python -m paper_1508_07982_amd.profiling trace-summary  RESULTS_DIR OUT.txt --command "..."
+            [--storage f32] [--workload sphere|slab]
     python -m paper_1508_07982_amd.profiling traffic-summary COPY_FETCH COPY_WRITE SWEEP_FETCH SWEEP_WRITE OUT.txt
-            --command "..."
+            --command "..." [--storage f32]
 
 The sweep workload is the benchmark grid (sphere shell, 4^3 roots of 32^3
-cells, 121.4 M cells) with the launch shape chosen by the autotuner, as in
-bench.py, stepped with one launch per level substep, so every sweep dispatch
-shows up in the trace.  FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are
-scaled by what the same counters read for a copy of a known byte count; the
-result is the HBM traffic of one finest-level sweep launch.
+cells, 121.4 M cells) or the slab + sphere grid of the batching form
+(5^3 roots of 16^3 cells, 8.57 M cells) with the launch shape chosen by the
+autotuner, as in bench.py, stepped with one launch per level substep, so
+every sweep dispatch shows up in the trace.  FETCH_SIZE and WRITE_SIZE (KiB
+per dispatch) are scaled by what the same counters read for the library's
+copy probe (lbm_probe_copy) of a known byte count; the result is the HBM
+traffic of one finest-level sweep launch.
 
 Both workloads run the autotuner first and then a mass reduction; only
 sweep dispatches after the first reduction kernel (the measured phase) enter
@@ -48,19 +52,74 @@ def sweep_sources_hash(storage: str = "f32") -> str:
 
 def run_copy():
     import torch
+    sys.path.insert(0, ROOT)
+    from paper_1508_07982_amd import lbm
     a = torch.zeros(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
     torch.cuda.synchronize()
-    print(f"copied {COPY_BYTES} bytes x 3", flush=True)
+    ms = lbm.probe_copy(b.data_ptr(), a.data_ptr(), COPY_BYTES, iters=2)  # warm-up + 2 copies
+    print(f"copied {COPY_BYTES} bytes x 3 with lbm_probe_copy: {COPY_BYTES / ms / 1e6:.1f} GB/s", flush=True)
 
 
-def run_sweep(storage: str, steps: int):
+def _workload(name: str):
+    from paper_1508_07982_amd import workloads as W
+    return W.config_sphere(32, 4) if name == "sphere" else W.config_slab_sphere(16, 5)
+
+
+def ceilings(blocks: int = 2368, n: int = 32, iters: int = 10):
+    """Bandwidth ceilings measured with the library's probes: a 1 GiB copy
+    (plain and nontemporal stores), and the sweep's access shape without
+    arithmetic (19 rows read and written per tile) over `blocks` blocks of
+    n^3 cells -- the finest level of the benchmark grid -- for every storage
+    width, workgroup size and tile order.  Returns a list of dicts."""
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_1508_07982_amd import lbm
+    out = []
+    a = torch.zeros(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for nt in (True, False):
+        ms = lbm.probe_copy(b.data_ptr(), a.data_ptr(), COPY_BYTES, iters=iters, nontemporal=nt)
+        out.append({"probe": "copy", "bytes": COPY_BYTES, "nontemporal": nt, "ms": ms,
+                    "GBps": 2 * COPY_BYTES / ms / 1e6})
+    del a, b
+    for s in (8, 4, 2):
+        nbytes = blocks * 19 * n ** 3 * s
+        src = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for lanes in (64, 128, 256):
+            for xcd in (False, True):
+                ms = lbm.probe_streams(dst.data_ptr(), src.data_ptr(), blocks, n, s, lanes, xcd, iters)
+                out.append({"probe": "sweep_shape", "elem_bytes": s, "blocks": blocks, "n": n, "lanes": lanes,
+                            "xcd": xcd, "ms": ms, "GBps": 2 * nbytes / ms / 1e6})
+        del src, dst
+    torch.cuda.synchronize()
+    return out
+
+
+def write_ceilings(out_path: str, command: str):
+    rows = ceilings()
+    with open(out_path, "w") as fh:
+        fh.write("# bandwidth ceilings from the library's probes (lbm_probe.h), HIP events, mean of 10 launches\n")
+        fh.write(f"# command: {command}\n")
+        fh.write("# GB/s = bytes read + bytes written per launch / mean launch time\n\n")
+        for r in rows:
+            if r["probe"] == "copy":
+                fh.write(f"copy {r['bytes']} B, {'nontemporal' if r['nontemporal'] else 'plain'} stores: "
+                         f"{r['ms']:.3f} ms, {r['GBps']:.1f} GB/s\n")
+            else:
+                fh.write(f"sweep shape, {r['elem_bytes']}-byte elements, {r['blocks']} blocks of {r['n']}^3, "
+                         f"{r['lanes']} lanes, {'XCD-grouped' if r['xcd'] else 'canonical'} order: "
+                         f"{r['ms']:.3f} ms, {r['GBps']:.1f} GB/s\n")
+    print(open(out_path).read(), flush=True)
+
+
+def run_sweep(storage: str, steps: int, workload: str = "sphere"):
     sys.path.insert(0, ROOT)
     from paper_1508_07982_amd import lbm
     from paper_1508_07982_amd import workloads as W
-    w = W.config_sphere(32, 4)
+    w = _workload(workload)
     g = lbm.Forest(w.R, w.n, w.max_level, refine=w.refine, storage=storage)
     rho, u = W.initial_field(w, g.leaves())
     g.set_level_omega(w.omega0)
@@ -77,11 +136,10 @@ def run_sweep(storage: str, steps: int):
     g.close()
 
 
-def _finest_tiles(storage: str = "f32"):
+def _finest_tiles(storage: str = "f32", workload: str = "sphere"):
     sys.path.insert(0, ROOT)
     from paper_1508_07982_amd import lbm
-    from paper_1508_07982_amd import workloads as W
-    w = W.config_sphere(32, 4)
+    w = _workload(workload)
     return {L: lbm.plan_level_stats(w.R, w.n, w.max_level, L, refine=w.refine, storage=storage)["work_tiles"]
             for L in range(w.max_level + 1)}
 
@@ -110,11 +168,11 @@ def _measured_from(db):
     return min(rows) if rows else 0
 
 
-def trace_summary(results: str, out: str, command: str):
+def trace_summary(results: str, out: str, command: str, storage: str = "f32", workload: str = "sphere"):
     db = _db(results)
     first = _measured_from(db)
     rows = list(db.execute("select name, duration, grid_x, workgroup_x, dispatch_id from kernels"))
-    tiles = _finest_tiles()
+    tiles = _finest_tiles(storage, workload)
     level_of_grid = {}
     for L, t in tiles.items():
         level_of_grid.setdefault(t, L)
@@ -222,13 +280,19 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     sub.add_parser("copy")
+    c = sub.add_parser("ceiling")
+    c.add_argument("out")
+    c.add_argument("--command", default="python3 -m paper_1508_07982_amd.profiling ceiling OUT")
     s = sub.add_parser("sweep")
     s.add_argument("--storage", default="f32")
     s.add_argument("--steps", type=int, default=2)
+    s.add_argument("--workload", default="sphere", choices=["sphere", "slab"])
     t = sub.add_parser("trace-summary")
     t.add_argument("results")
     t.add_argument("out")
     t.add_argument("--command", required=True)
+    t.add_argument("--storage", default="f32")
+    t.add_argument("--workload", default="sphere", choices=["sphere", "slab"])
     tr = sub.add_parser("traffic-summary")
     for k in ("copy_fetch", "copy_write", "sweep_fetch", "sweep_write", "out"):
         tr.add_argument(k)
@@ -237,10 +301,12 @@ def main():
     a = ap.parse_args()
     if a.cmd == "copy":
         run_copy()
+    elif a.cmd == "ceiling":
+        write_ceilings(a.out, a.command)
     elif a.cmd == "sweep":
-        run_sweep(a.storage, a.steps)
+        run_sweep(a.storage, a.steps, a.workload)
     elif a.cmd == "trace-summary":
-        trace_summary(a.results, a.out, a.command)
+        trace_summary(a.results, a.out, a.command, a.storage, a.workload)
     else:
         traffic_summary(a.copy_fetch, a.copy_write, a.sweep_fetch, a.sweep_write, a.out, a.command, a.storage)
 

@@ -115,7 +115,11 @@ def test_trt_off_is_srt_and_refusals():
         g.step_coarse(3)
         outs.append(g.get_pdfs())
         if switch:
-            g.set_trt_force(LAMBDA_EO, A0)
+            # the acceleration is part of the stored state: refused once set
+            with pytest.raises(lbm.LBMError) as e:
+                g.set_trt_force(LAMBDA_EO, A0)
+            assert e.value.name == "LBM_E_STATE"
+            g.set_trt_force(LAMBDA_EO, None)  # the TRT rates alone may change
             with pytest.raises(lbm.LBMError):
                 g.regrid(np.zeros(len(g.leaves()), dtype=np.int8))
             with pytest.raises(lbm.LBMError):
