@@ -173,6 +173,19 @@ int lbm_step_coarse(lbm_forest *f, int n_steps);
  * Synchronizes the stream. */
 int lbm_get_moments(lbm_forest *f, double *rho, double *u);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * output as lbm_get_moments, computed by the same kernel, without any
+ * allocation.  The cells pass through a staging array of the library's own
+ * that each device holds for the life of the process (16 MiB: chunks of at
+ * most 524,288 cells, so any forest size is accepted).  Every call on a
+ * device shares that device's array: calls that overlap on one device (from
+ * several threads, or forests on different streams) race and must be
+ * serialized by the caller.  Synchronizes the forest's stream.
+ * Errors: LBM_E_INVALID, LBM_E_STATE (a failed table lookup in an earlier
+ * sweep), LBM_E_HIP. */
+int lbm_get_moments_static(lbm_forest *f, double *rho, double *u);
+
 /* Volume-weighted mass and momentum, M = sum_L 8^-L sum_{cells} sum_a f_a
  * and J = sum_L 8^-L sum sum e_a f_a, accumulated in FP64 on the device.
  * The weight of a level-L cell is its volume (dx_L / dx_0)^3 = 8^-L in

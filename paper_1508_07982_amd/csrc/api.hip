@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -347,6 +348,30 @@ int check_err_flag(lbm_forest* f) {
 }
 
 const void* current_buffer(const lbm_forest* f, int L) { return f->lv[L].buf[f->rot[L]]; }
+
+// Staging memory of lbm_get_moments_static: a file-scope device array, so
+// that the call allocates nothing.  Each device holds its own copy, at an
+// address that hipGetSymbolAddress gives once per device (the array's name
+// is not a device address in host code).
+constexpr int64_t kStageCells = int64_t(1) << 19;  // 524,288 cells per chunk: rho + u = 16 MiB
+static __device__ __align__(256) double scratch[4 * kStageCells];
+constexpr int kMaxDevices = 64;
+std::mutex g_stage_mu;
+double* g_stage[kMaxDevices] = {};
+
+// The calling thread's current device must be `device`.
+int moments_stage(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(LBM_E_INVALID, "device ordinal %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_stage_mu);
+  if (!g_stage[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(LBM_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_stage[device] = static_cast<double*>(p);
+  }
+  *out = g_stage[device];
+  return LBM_OK;
+}
 
 void* current_buffer_mut(lbm_forest* f, int L) { return f->lv[L].buf[f->rot[L]]; }
 
@@ -1044,7 +1069,7 @@ int lbm_get_moments(lbm_forest* f, double* rho, double* u) {
     double* d = nullptr;
     HIP_TRY(hipMalloc(&d, v.ncells * 4 * sizeof(double)));
     auto body = [&]() -> int {
-      HIP_TRY(launch_moments(f->storage, f->n, current_buffer(f, int(L)), d, d + v.ncells, v.ncells,
+      HIP_TRY(launch_moments(f->storage, f->n, current_buffer(f, int(L)), d, d + v.ncells, 0, v.ncells,
                              level_accel(f, int(L)), f->stream));
       HIP_TRY(hipMemcpyAsync(rho + off, d, v.ncells * sizeof(double), hipMemcpyDeviceToHost, f->stream));
       HIP_TRY(hipMemcpyAsync(u + 3 * off, d + v.ncells, v.ncells * 3 * sizeof(double), hipMemcpyDeviceToHost,
@@ -1057,6 +1082,33 @@ int lbm_get_moments(lbm_forest* f, double* rho, double* u) {
     if (rc) return rc;
     off += v.ncells;
   }
+  return LBM_OK;
+}
+
+int lbm_get_moments_static(lbm_forest* f, double* rho, double* u) {
+  if (!f || !rho || !u) return fail(LBM_E_INVALID, "null pointer");
+  HIP_TRY(hipSetDevice(f->device));
+  double* stage = nullptr;
+  int rc = moments_stage(f->device, &stage);
+  if (rc) return rc;
+  if ((rc = check_err_flag(f))) return rc;
+  int64_t off = 0;
+  for (size_t L = 0; L < f->lv.size(); ++L) {
+    const LevelDev& v = f->lv[L];
+    // chunks of at most kStageCells cells: rho in stage[0, kStageCells),
+    // u in stage[kStageCells, 4 kStageCells); the stream orders each chunk's
+    // copies before the next chunk's kernel overwrites the stage
+    for (int64_t c0 = 0; c0 < v.ncells; c0 += kStageCells) {
+      const int64_t m = std::min<int64_t>(kStageCells, v.ncells - c0);
+      HIP_TRY(launch_moments(f->storage, f->n, current_buffer(f, int(L)), stage, stage + kStageCells, c0, m,
+                             level_accel(f, int(L)), f->stream));
+      HIP_TRY(hipMemcpyAsync(rho + off + c0, stage, m * sizeof(double), hipMemcpyDeviceToHost, f->stream));
+      HIP_TRY(hipMemcpyAsync(u + 3 * (off + c0), stage + kStageCells, m * 3 * sizeof(double), hipMemcpyDeviceToHost,
+                             f->stream));
+    }
+    off += v.ncells;
+  }
+  HIP_TRY(hipStreamSynchronize(f->stream));
   return LBM_OK;
 }
 

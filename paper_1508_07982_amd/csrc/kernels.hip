@@ -39,10 +39,12 @@ __global__ void init_kernel(S* buf, const double* rho, const double* u, int64_t 
   }
 }
 
+// Cells [first, first + count) of a level; output index relative to first.
 template <typename S, int N>
-__global__ void moments_kernel(const S* buf, double* rho, double* u, int64_t ncells, Accel acc) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= ncells) return;
+__global__ void moments_kernel(const S* buf, double* rho, double* u, int64_t first, int64_t count, Accel acc) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int64_t idx = first + t;
   double s = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int a = 0; a < 19; ++a) {
@@ -52,10 +54,10 @@ __global__ void moments_kernel(const S* buf, double* rho, double* u, int64_t nce
     jy += ey(a) * h;
     jz += ez(a) * h;
   }
-  rho[idx] = 1.0 + s;
-  u[3 * idx] = jx - 0.5 * acc.a[0];
-  u[3 * idx + 1] = jy - 0.5 * acc.a[1];
-  u[3 * idx + 2] = jz - 0.5 * acc.a[2];
+  rho[t] = 1.0 + s;
+  u[3 * t] = jx - 0.5 * acc.a[0];
+  u[3 * t + 1] = jy - 0.5 * acc.a[1];
+  u[3 * t + 2] = jz - 0.5 * acc.a[2];
 }
 
 template <typename S, int N>
@@ -321,14 +323,14 @@ hipError_t launch_init(int storage, int n, void* buf, const double* rho, const d
   });
 }
 
-hipError_t launch_moments(int storage, int n, const void* buf, double* rho, double* u,
-                          int64_t ncells, Accel accel, hipStream_t stream) {
-  if (ncells <= 0) return hipSuccess;
+hipError_t launch_moments(int storage, int n, const void* buf, double* rho, double* u, int64_t first,
+                          int64_t count, Accel accel, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
   return dispatch(storage, n, [&](auto s, auto nn) {
     using S = decltype(s);
     constexpr int N = decltype(nn)::value;
-    hipLaunchKernelGGL((moments_kernel<S, N>), dim3(grid_for(ncells, 256)), dim3(256), 0, stream,
-                       static_cast<const S*>(buf), rho, u, ncells, accel);
+    hipLaunchKernelGGL((moments_kernel<S, N>), dim3(grid_for(count, 256)), dim3(256), 0, stream,
+                       static_cast<const S*>(buf), rho, u, first, count, accel);
     return hipGetLastError();
   });
 }

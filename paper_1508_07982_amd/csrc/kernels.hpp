@@ -107,9 +107,10 @@ hipError_t launch_init(int storage, int n, void* buf, const double* rho, const d
                        int64_t ncells, Accel accel, hipStream_t stream);
 
 // rho = 1 + sum h, u = sum e h - a / 2: the velocity of the pre-collision
-// state (sum e h - a) plus a / 2 (section 2, external forces).
-hipError_t launch_moments(int storage, int n, const void* buf, double* rho, double* u,
-                          int64_t ncells, Accel accel, hipStream_t stream);
+// state (sum e h - a) plus a / 2 (section 2, external forces).  Cells
+// [first, first + count) of the level; rho[count], u[count][3].
+hipError_t launch_moments(int storage, int n, const void* buf, double* rho, double* u, int64_t first,
+                          int64_t count, Accel accel, hipStream_t stream);
 
 // Raw shifted PDFs, FP64 [cell][19].
 hipError_t launch_get_pdfs(int storage, int n, const void* buf, double* h, int64_t ncells,

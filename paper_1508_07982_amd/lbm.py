@@ -69,6 +69,7 @@ _SIGNATURES = {
     "lbm_init_pdfs": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_step_coarse": [ctypes.c_void_p, ctypes.c_int],
     "lbm_get_moments": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_get_moments_static": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_mass": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
     "lbm_set_schedule": [ctypes.c_void_p, ctypes.c_int],
     "lbm_set_launch": [ctypes.c_void_p, ctypes.c_int],
@@ -385,6 +386,15 @@ class Forest:
         rho = np.empty(N)
         u = np.empty((N, 3))
         _check(self._lib.lbm_get_moments(self._h, _ptr(rho), _ptr(u)))
+        return rho, u
+
+    def moments_static(self):
+        """As moments(), through lbm_get_moments_static (no device
+        allocation; calls overlapping on one device race)."""
+        N = self.num_cells(-1)
+        rho = np.empty(N)
+        u = np.empty((N, 3))
+        _check(self._lib.lbm_get_moments_static(self._h, _ptr(rho), _ptr(u)))
         return rho, u
 
     def mass(self):
