@@ -174,3 +174,24 @@ def gradient(params, X, t, mean, std):
     gW1 = dA1.T @ Xh
     gb1 = dA1.sum(0)
     return np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gw3, [gb3]])
+
+
+def adam(params, grad_fn, steps, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """`steps` Adam updates (Kingma & Ba, "Adam: a method for stochastic
+    optimization", 2015, Algorithm 1) of params with the gradient grad_fn(p):
+    first and second moment estimates m, v with bias corrections
+    1 - beta^t, p <- p - lr m_hat / (sqrt(v_hat) + eps).  Returns the
+    parameters after every step, (steps, P)."""
+    p = np.array(params, dtype=np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    out = []
+    for t in range(1, steps + 1):
+        g = grad_fn(p)
+        m = beta1 * m + (1.0 - beta1) * g
+        v = beta2 * v + (1.0 - beta2) * g * g
+        m_hat = m / (1.0 - beta1 ** t)
+        v_hat = v / (1.0 - beta2 ** t)
+        p = p - lr * m_hat / (np.sqrt(v_hat) + eps)
+        out.append(p.copy())
+    return np.array(out)

@@ -98,6 +98,31 @@ def test_mlp_gradient_matches_oracle():
     m.close()
 
 
+def test_mlp_adam_steps_match_oracle():
+    """Three full-batch training steps (batch = n, so the shuffle does not
+    change the mean gradient) against the FP64 Adam of the oracle from the
+    same initial parameters: the parameter changes agree to FP32 accuracy."""
+    X, t = _mlp_inputs(7)
+    m = lbm.MLP(seed=3)
+    m.fit_normalization(X)
+    p0 = m.params().astype(np.float64)
+    mean, std = X.mean(0), np.maximum(X.std(0), 1e-6)
+    lr = 1e-3
+    want = ind.adam(p0, lambda p: ind.gradient(p, X, t, mean, std), 3, lr)
+    g0 = np.abs(ind.gradient(p0, X, t, mean, std))
+    # parameters whose gradient is far above FP32 rounding of the sums: Adam
+    # moves them by about lr per step whatever the gradient's size, so a
+    # gradient at rounding level would decide a sign
+    live = g0 > 1e-5 * g0.max()
+    for step in range(3):
+        m.train(X, t, epochs=1, batch=len(X), lr=lr, seed=step)
+        got = m.params().astype(np.float64)
+        d_got, d_want = got - p0, want[step] - p0
+        assert np.max(np.abs(d_got[live] - d_want[live])) < 2e-2 * lr * (step + 1), step
+        assert np.max(np.abs(d_got)) <= 1.1 * lr * (step + 1)
+    m.close()
+
+
 def test_mlp_training_lowers_loss():
     rng = np.random.default_rng(6)
     X = rng.normal(size=(2048, ind.NFEAT))

@@ -13,7 +13,10 @@ that the definitions imply, not by re-running the oracle's formulas:
   collision, so mean neq = |1 - omega| delta ||g|| / rho;
 * density linear along x gives mean and std of rho in closed form;
 * the MLP with identity hidden layers computes sigmoid(sum relu(x_hat));
-* the analytic gradient matches central differences of the loss.
+* the analytic gradient matches central differences of the loss;
+* Adam with a constant gradient moves every parameter by lr g / (|g| + eps)
+  per step, and its moment recursion written out by hand for two steps on a
+  quadratic gives the same path.
 """
 
 import numpy as np
@@ -59,6 +62,10 @@ def test_linear_field_curl_jumps_and_zero_neq():
     assert np.allclose(feat[:, 7], np.log10(np.hypot(a, c) * n / 2 + 1e-12), atol=1e-12)
     assert np.allclose(feat[:, 8], -12.0, atol=1e-3)
     assert np.allclose(feat[:, 9], np.log10(curl + 1e-12), atol=1e-12)
+    # rms |u - mean u|: each component is linear in one index, whose
+    # variance over 0..n-1 is (n^2 - 1) / 12
+    rms = np.sqrt((a * a + b * b + c * c) * (n * n - 1) / 12.0)
+    assert np.allclose(feat[:, 4], np.log10(rms + 1e-12), atol=1e-12)
     # level / Lmax and the density features of rho = 1
     levels = np.concatenate([np.full(o.n_int(L) // n ** 3, L) for L in range(o.num_levels)])
     assert np.array_equal(feat[:, 0], levels / 1.0)
@@ -114,6 +121,59 @@ def test_non_equilibrium_norm_of_ghost_mode():
         want = abs(1.0 - o.omega[L]) * delta * 2.0 / rho0
         sl = slice(0, nb0) if L == 0 else slice(nb0, None)
         assert np.allclose(crit[sl, 1], want, rtol=1e-10, atol=0)
+
+
+def test_non_equilibrium_of_one_cell_mean_and_max():
+    """The ghost mode g on one cell of every block: the block's mean
+    non-equilibrium norm is |1 - omega| delta ||g|| / rho / n^3 and its
+    maximum (feature 11) |1 - omega| delta ||g|| / rho."""
+    n = 8
+    o = RefinedOracle(two_level(n), 1.3)
+    e, _ = orc.lattice()
+    g = np.zeros(19)
+    g[[1, 2]] = 1.0   # the two x faces
+    g[[5, 6]] = -1.0  # the two z faces
+    assert g.sum() == 0 and np.all(g @ e == 0)
+    delta, rho0, cell = 2e-3, 0.99, 37
+    for L in range(o.num_levels):
+        m = o.n_int(L)
+        f = orc.equilibrium(np.full(m, rho0), np.tile([-0.01, 0.02, 0.005], (m, 1)))
+        f[cell::n ** 3] += delta * g
+        o.set_interior_pdfs(L, f)
+    feat, crit = ind.block_indicators(o)
+    nb0 = o.n_int(0) // n ** 3
+    for L in range(o.num_levels):
+        peak = abs(1.0 - o.omega[L]) * delta * 2.0 / rho0
+        sl = slice(0, nb0) if L == 0 else slice(nb0, None)
+        assert np.allclose(crit[sl, 1], peak / n ** 3, rtol=1e-9, atol=0)
+        assert np.allclose(feat[sl, 10], np.log10(peak / n ** 3 + 1e-12), atol=1e-9)
+        assert np.allclose(feat[sl, 11], np.log10(peak + 1e-12), atol=1e-9)
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias-corrected moments are g and g^2
+    at every step, so each Adam step moves p by -lr g / (|g| + eps)."""
+    g = np.array([3.0, -0.5, 0.0, 2e-9, -1e4])
+    p0 = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    lr = 1e-2
+    path = ind.adam(p0, lambda p: g, 4, lr)
+    step = -lr * g / (np.abs(g) + 1e-8)
+    for t in range(4):
+        assert np.allclose(path[t], p0 + (t + 1) * step, rtol=0, atol=1e-14)
+
+
+def test_adam_on_quadratic_descends_and_follows_the_moments():
+    """On f(p) = |p|^2 / 2 (gradient p) Adam's first step is lr sign(p), and
+    the recursion of m and v written out for two steps gives the second."""
+    p0 = np.array([0.5, -2.0, 1e-3])
+    lr = 0.1
+    path = ind.adam(p0, lambda p: p, 2, lr)
+    p1 = p0 - lr * p0 / (np.abs(p0) + 1e-8)
+    assert np.allclose(path[0], p1, rtol=0, atol=1e-15)
+    m = 0.9 * 0.1 * p0 + 0.1 * p1
+    v = 0.999 * 0.001 * p0 ** 2 + 0.001 * p1 ** 2
+    p2 = p1 - lr * (m / (1 - 0.81)) / (np.sqrt(v / (1 - 0.999 ** 2)) + 1e-8)
+    assert np.allclose(path[1], p2, rtol=0, atol=1e-15)
 
 
 def test_plain_targets_cases():

@@ -5,6 +5,9 @@
   implementation of collide-then-stream (eq. collide, eq. stream).
 * A shear wave decays at the rate nu k^2 with nu from eq. viscosity_srt
   (nu = (1/omega - 1/2)/3 in lattice units), up to an O(k^2) lattice error.
+* A small-amplitude 3-D Taylor-Green field, u = A (sin kx cos ky cos kz,
+  -cos kx sin ky cos kz, 0), is a Stokes mode with |k|^2 = 3 k^2: its
+  kinetic energy decays as exp(-6 nu k^2 t), again up to O(k^2).
 """
 
 import math
@@ -73,3 +76,31 @@ def test_shear_wave_viscosity():
     assert err32 < 5e-3
     # O(k^2) lattice error: halving k cuts it by about 4
     assert 3.5 < err16 / err32 < 4.5
+
+
+def _taylor_green_rate(N, omega=1.6, A=1e-3, n=8):
+    """Fitted energy decay rate / (6 nu k^2) on a single-level N^3 grid."""
+    o = RefinedOracle(Forest.build((N // n,) * 3, n, 0, None), omega)
+    xyz, _ = _dense_index(o)
+    k = 2 * math.pi / N
+    x, y, z = [(xyz[:, i] + 0.5) * k for i in range(3)]
+    u = np.zeros((len(xyz), 3))
+    u[:, 0] = A * np.sin(x) * np.cos(y) * np.cos(z)
+    u[:, 1] = -A * np.cos(x) * np.sin(y) * np.cos(z)
+    o.init_pdfs(np.ones(len(xyz)), u)
+    steps = (N, 5 * N)
+    energy, t = {}, 0
+    for target in steps:
+        o.step(target - t)
+        t = target
+        _, uu = o.moments()
+        energy[target] = np.sum(uu ** 2)
+    nu = (1.0 / omega - 0.5) / 3.0
+    return -math.log(energy[steps[1]] / energy[steps[0]]) / (steps[1] - steps[0]) / (6 * nu * k * k)
+
+
+def test_taylor_green_energy_decay():
+    r16 = _taylor_green_rate(16)
+    r32 = _taylor_green_rate(32)
+    assert abs(r32 - 1.0) < 1.5e-2
+    assert 3.5 < abs(r16 - 1.0) / abs(r32 - 1.0) < 4.7
