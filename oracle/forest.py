@@ -22,6 +22,11 @@ Readings:
 
 A leaf is the tuple (L, x, y, z): level and integer block position on that
 level; level L has R_a * 2^L positions along axis a.
+
+An axis may be non-periodic (section 2.2: domain boundaries get a boundary
+treatment instead of the periodic copy): positions beyond its ends lie
+outside the domain, are no neighbours for the 2:1 balance and hold no-slip
+walls (see tables.py).
 """
 
 from __future__ import annotations
@@ -48,9 +53,10 @@ def morton_key(x: int, y: int, z: int) -> int:
 class Forest:
     """A 2:1 balanced forest: root grid R, n^3 cells per block, leaf set."""
 
-    def __init__(self, roots, n: int, leaves):
+    def __init__(self, roots, n: int, leaves, periodic=(True, True, True)):
         self.R = tuple(int(r) for r in roots)
         self.n = int(n)
+        self.periodic = tuple(bool(p) for p in periodic)
         self.leaves = set(tuple(int(v) for v in leaf) for leaf in leaves)
         if not self.leaves:
             raise ValueError("empty forest")
@@ -58,7 +64,7 @@ class Forest:
 
     # -- construction --------------------------------------------------------
     @classmethod
-    def build(cls, roots, n: int, max_level: int, refine=None):
+    def build(cls, roots, n: int, max_level: int, refine=None, periodic=(True, True, True)):
         """Roots, then callback splits level by level, then 2:1 balance."""
         R = tuple(int(r) for r in roots)
         leaves = {(0, x, y, z) for x in range(R[0]) for y in range(R[1]) for z in range(R[2])}
@@ -69,7 +75,7 @@ class Forest:
                 if refine(leaf[0], leaf[1], leaf[2], leaf[3]):
                     leaves.remove(leaf)
                     leaves.update(cls._children(leaf))
-        forest = cls(R, n, leaves)
+        forest = cls(R, n, leaves, periodic)
         forest.balance()
         forest.check_cover()
         return forest
@@ -82,9 +88,11 @@ class Forest:
 
     def covering_leaf(self, level: int, pos):
         """Leaf of level <= `level` that contains block position `pos` of
-        `level` (wrapped periodically), or None if that position is split
-        into finer leaves."""
+        `level` (wrapped along periodic axes), or None if that position is
+        split into finer leaves or lies beyond a non-periodic end."""
         dims = [r << level for r in self.R]
+        if any(not self.periodic[a] and not 0 <= int(pos[a]) < dims[a] for a in range(3)):
+            return None
         p = [int(pos[a]) % dims[a] for a in range(3)]
         for lv in range(level, -1, -1):
             s = level - lv

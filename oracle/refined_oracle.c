@@ -18,7 +18,9 @@
  *                 F_a = w_a rho0 (e_a . a) / c_s^2 is added; u in f^eq is
  *                 the unmodified sum e f / rho0
  *   explode       eq. ctof: every E_L cell takes its parent's 19 PDFs
- *   stream        pull: f(x) <- f(x - e_a) for x in I_L u H_L (eq. stream)
+ *   stream        pull: f(x) <- f(x - e_a) for x in I_L u H_L (eq. stream);
+ *                 from a no-slip boundary cell: x's own opposite value
+ *                 (halfway bounce-back, section 2.2)
  *   coalesce      eq. ftoc: 1/8 of the sum over the 8 children, for the
  *                 (cell, direction) pairs of the coalescence set
  *   step          Algorithm 1, NonUniformTimeStep(L), in the paper's order
@@ -178,13 +180,27 @@ void orc_stream_calls(int64_t *out, int num_levels, int reset) {
   }
 }
 
+/* the direction opposite to a */
+static int opposite(int a) {
+  int b = 0;
+  while (EV[b][0] != -EV[a][0] || EV[b][1] != -EV[a][1] || EV[b][2] != -EV[a][2]) ++b;
+  return b;
+}
+
+#define ORC_WALL (-2) /* pull source beyond a non-periodic end (tables.py) */
+
+/* pull stream of I_L u H_L.  A source in a boundary cell (no-slip wall,
+   section 2.2) holds, after the boundary treatment, the value x sent
+   towards it reversed: x's own value of the opposite direction (halfway
+   bounce-back). */
 static void stream(orc_level *lv, int L) {
   if (L < ORC_MAX_LEVELS) stream_calls[L]++;
 #pragma omp parallel for schedule(static)
   for (int64_t x = 0; x < lv->n_live; ++x) {
     for (int a = 0; a < Q; ++a) {
       const int32_t s = lv->pull[Q * x + a];
-      lv->G[Q * x + a] = (s >= 0) ? lv->F[Q * (int64_t)s + a] : NAN;
+      lv->G[Q * x + a] = (s >= 0) ? lv->F[Q * (int64_t)s + a]
+                         : (s == ORC_WALL ? lv->F[Q * x + opposite(a)] : NAN);
     }
   }
 #pragma omp parallel for schedule(static)

@@ -54,7 +54,7 @@ def regrid_forest(forest: Forest, flags, max_level: int) -> Forest:
             new.update(_children(leaf))
         elif fl < 0 and leaf[0] > 0:
             coarsen.add(leaf)
-    f2 = Forest(forest.R, forest.n, new)
+    f2 = Forest(forest.R, forest.n, new, forest.periodic)
     f2.balance()
     Lm = max(leaf[0] for leaf in f2.leaves) + 1
     for L in range(max(leaf[0] for leaf in f2.leaves), 0, -1):

@@ -15,6 +15,16 @@ Definitions (section 2.3, section 4, section 4.3, section 4.4):
 * Stream (pull form): for x in I_L u H_L and every direction a, the new value
   is the old value at x - e_a.  A source inside region(L+1) has no level-L
   value; such an (x, a) must be in the coalescence set.
+* Walls (section 2.2): along a non-periodic axis every cell beyond the
+  domain is a no-slip boundary cell.  The boundary treatment stores, after
+  the collision, in the boundary cell the value the neighbouring fluid cell
+  sent towards it, reversed; the fluid cell then pulls it unchanged.  So a
+  pull of (x, a) from a boundary cell x - e_a takes x's own value of the
+  opposite direction (halfway bounce-back: the wall lies midway between the
+  cells).  Section 4.1 extends the boundary treatment to the two innermost
+  ghost layers of fine blocks, so halo cells bounce back their own
+  (exploded) values the same way.  Cells outside the domain are never
+  interior, ghost or explosion cells and never take part in coalescence.
 * Coalescence set P_L.  Section 4.4 sends only the PDFs "streaming into" the
   coarse block from the two innermost fine ghost layers, averaged over the 8
   fine cells of a coarse cell (eq. ftoc).  Reading used by default
@@ -35,6 +45,8 @@ from __future__ import annotations
 import numpy as np
 
 from .forest import NEIGHBOUR_OFFSETS
+
+WALL = -2  # pull-table code: the source lies beyond a non-periodic end (bounce-back)
 
 
 def d3q19_velocities() -> np.ndarray:
@@ -75,12 +87,25 @@ def _pattern_distance(n: int, offsets) -> np.ndarray:
     return dist
 
 
+def _shift(arr: np.ndarray, d, periodic) -> np.ndarray:
+    """arr shifted so that out[p] = arr[p + d]; along a non-periodic axis the
+    entries beyond the end are False (no block there)."""
+    out = np.roll(arr, shift=(-d[0], -d[1], -d[2]), axis=(0, 1, 2))
+    for ax in range(3):
+        if not periodic[ax] and d[ax] != 0:
+            sl = [slice(None)] * 3
+            sl[ax] = slice(-1, None) if d[ax] > 0 else slice(0, 1)
+            out[tuple(sl)] = False
+    return out
+
+
 class LevelCells:
     """Cell sets I_L, H_L, E_L of one level and a coordinate -> index map."""
 
     def __init__(self, forest, L: int):
         n = forest.n
         self.L, self.n = L, n
+        self.periodic = tuple(getattr(forest, "periodic", (True, True, True)))
         self.n3 = n ** 3
         self.pdims = np.array([r << L for r in forest.R], dtype=np.int64)
         self.cdims = self.pdims * n
@@ -98,8 +123,8 @@ class LevelCells:
         touch = np.zeros(self.cov.shape, dtype=bool)
         pattern = np.zeros(self.cov.shape, dtype=np.int64)
         for bit, d in enumerate(NEIGHBOUR_OFFSETS):
-            # neighbour at offset d of position p is real  <=> roll by -d
-            nbr_real = np.roll(is_real, shift=(-d[0], -d[1], -d[2]), axis=(0, 1, 2))
+            # neighbour at offset d of position p is real  <=> shift by -d
+            nbr_real = _shift(is_real, d, self.periodic)
             touch |= nbr_real
             pattern |= nbr_real.astype(np.int64) << bit
         cand = touch & ~is_real & (self.cov < L)
@@ -144,9 +169,19 @@ class LevelCells:
             coords[self.n_live:] = gall[e_mask]
         self.coords = coords
 
+    def outside(self, g: np.ndarray) -> np.ndarray:
+        """Whether global level-L cells g lie beyond a non-periodic end."""
+        out = np.zeros(len(g), dtype=bool)
+        for ax in range(3):
+            if not self.periodic[ax]:
+                out |= (g[:, ax] < 0) | (g[:, ax] >= self.cdims[ax])
+        return out
+
     def lookup(self, g: np.ndarray):
-        """Index in S_L of global level-L cells g (M, 3), -1 if not stored;
-        and whether each cell lies in region(L+1)."""
+        """Index in S_L of global level-L cells g (M, 3), -1 if not stored,
+        WALL beyond a non-periodic end; and whether each cell lies in
+        region(L+1)."""
+        wall = self.outside(g)
         g = np.mod(g, self.cdims)
         pos = g // self.n
         loc = g % self.n
@@ -159,14 +194,16 @@ class LevelCells:
         idx[m] = rs[m] * self.n3 + lin[m]
         m2 = (~m) & (gs >= 0)
         idx[m2] = self.ghost_index[gs[m2], lin[m2]]
-        fine = self.cov[pos_t] == self.finer
+        fine = (self.cov[pos_t] == self.finer) & ~wall
+        idx[wall] = WALL
         return idx, fine
 
     def in_interior(self, g: np.ndarray) -> np.ndarray:
         """Whether global level-L cells g lie in I_L."""
+        wall = self.outside(g)
         g = np.mod(g, self.cdims)
         pos = g // self.n
-        return self.cov[(pos[:, 0], pos[:, 1], pos[:, 2])] == self.L
+        return (self.cov[(pos[:, 0], pos[:, 1], pos[:, 2])] == self.L) & ~wall
 
 
 class LevelTables:
@@ -180,7 +217,7 @@ class LevelTables:
         pull = np.empty((cells.n_live, 19), dtype=np.int64)
         for a in range(19):
             idx, fine = cells.lookup(live - E[a])
-            bad = (idx < 0) & ~(fine & (np.arange(cells.n_live) < cells.n_int))
+            bad = (idx == -1) & ~(fine & (np.arange(cells.n_live) < cells.n_int))
             if np.any(bad):
                 raise AssertionError(f"level {L}: stream source missing for direction {a}")
             pull[:, a] = idx
@@ -242,7 +279,7 @@ class LevelTables:
             self.coal_child = np.zeros((0, 8), dtype=np.int32)
 
         # every interior pull from region(L+1) must be overwritten by coalescence
-        missing = np.argwhere(self.pull[:cells.n_int] < 0)
+        missing = np.argwhere(self.pull[:cells.n_int] == -1)
         if len(missing):
             have = set(zip(self.coal_cell.tolist(), self.coal_dir.tolist()))
             for x, a in missing.tolist():
