@@ -5,9 +5,10 @@
  * balanced forest of octrees (Schornbaum & Ruede, "Massively parallel
  * algorithms for the lattice Boltzmann method on non-uniform grids"):
  *
- *   - the domain is a periodic grid of R_x x R_y x R_z root blocks; a block
- *     is split into 8 children of half its size; every block on every level
- *     holds n^3 cells, so level interfaces coincide with block faces
+ *   - the domain is a grid of R_x x R_y x R_z root blocks, periodic along
+ *     each axis or closed by no-slip walls (section 2.2); a block is split
+ *     into 8 children of half its size; every block on every level holds
+ *     n^3 cells, so level interfaces coincide with block faces
  *     (section 3.2, section 4);
  *   - neighbouring blocks differ by at most one level, counting face, edge
  *     and corner neighbours across the periodic wrap (section 2.3);
@@ -75,13 +76,23 @@ typedef struct lbm_forest lbm_forest;
 
 /* Refinement callback (section 3.3: user callbacks mark blocks for
  * refinement).  Asked once for every leaf of level `level` < max_level at
- * integer block position (x, y, z) of that level; nonzero = split it. */
+ * integer block position (x, y, z) of that level; nonzero = split it.  The
+ * block covers [x, x + 1) x [y, y + 1) x [z, z + 1) in units of level-`level`
+ * blocks, i.e. the box 2^-level (x, y, z) + [0, 2^-level)^3 in root-block
+ * units; integer positions are passed instead of floating-point boxes so
+ * that a callback decides exactly on the block lattice. */
 typedef int (*lbm_refine_fn)(int level, int x, int y, int z, void *user);
 
 typedef struct {
   int root_blocks[3];     /* R_x, R_y, R_z >= 1                                 */
   int cells_per_block;    /* n in {4, 8, 16, 32}                                 */
   int max_level;          /* deepest level allowed, 0 .. 20                       */
+  int periodic[3];        /* per axis: 1 periodic; 0 a no-slip wall at both ends
+                             (section 2.2: halfway bounce-back, the wall midway
+                             between the last cell and the boundary cell beyond;
+                             applied on every level and in the fine ghost
+                             layers, section 4.1).  Positions beyond a wall are
+                             no neighbours for the 2:1 balance.                  */
   const int32_t *leaves;  /* optional explicit leaf list [num_leaves][4] =
                              (L, x, y, z); must tile the domain exactly once    */
   int64_t num_leaves;
@@ -194,6 +205,21 @@ int lbm_get_moments_static(lbm_forest *f, double *rho, double *u);
  * levels (section 4.4).  The sum covers the stored (post-collision) state.
  * LBM_E_NONFINITE if NaN or Inf appears.  Synchronizes the stream. */
 int lbm_mass(lbm_forest *f, double *mass, double momentum[3]);
+
+/* FP64 accumulation check of the coalescence (eq. ftoc, section 4.4).  With
+ * FP32 or FP16 storage the 8-child sums are formed in FP32; with the check
+ * on (on != 0; off by default) every coalescence launch also sums the same
+ * loaded values in FP64.  The stored results do not change.  Invalidates
+ * captured graphs. */
+int lbm_set_coalescence_check(lbm_forest *f, int on);
+
+/* Figures of the check since the last call, which resets them:
+ * out[0] = largest |mean - FP64 mean| over the coalesced pairs, out[1] =
+ * largest ratio |sum - FP64 sum| / (gamma_7 sum |v|), gamma_7 = 7u/(1 - 7u)
+ * the error bound of recursive summation of 8 terms in the compute type of
+ * unit roundoff u (at most 1 for a correct sum), out[2] = pairs checked.
+ * Synchronizes the stream. */
+int lbm_coalescence_check(lbm_forest *f, double out[3]);
 
 /* Schedule of lbm_step_coarse: LBM_SCHED_GRAPH (default), _DIRECT or
  * _PER_BLOCK.  All three give bitwise identical results. */

@@ -261,6 +261,8 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
     c.coal.nbr = d.nbr;
     c.coal.fine_nbr = d.fine_nbr;
     c.coal.fine_slot = d.fine_slot;
+    c.coal.check = f->coal_check ? f->d_check : nullptr;
+    c.coal.err = f->d_err;
     ops.push_back(c);
   }
   ops.push_back(op);
@@ -416,16 +418,24 @@ static int validate_and_build(const lbm_forest_desc* d, Forest& forest, std::str
     err = "num_leaves without leaves";
     return LBM_E_INVALID;
   }
+  bool periodic[3];
+  for (int a = 0; a < 3; ++a) {
+    if (d->periodic[a] != 0 && d->periodic[a] != 1) {
+      err = "periodic flags must be 0 or 1";
+      return LBM_E_INVALID;
+    }
+    periodic[a] = d->periodic[a] != 0;
+  }
   int rc;
   if (d->leaves) {
-    rc = forest.build_from_leaves(d->root_blocks, n, d->leaves, d->num_leaves, d->balance != 0, err);
+    rc = forest.build_from_leaves(d->root_blocks, n, periodic, d->leaves, d->num_leaves, d->balance != 0, err);
     if (rc == LBM_OK && forest.max_level > d->max_level) {
       err = "leaf level above max_level";
       return LBM_E_INVALID;
     }
     return rc;
   }
-  return forest.build_from_callback(d->root_blocks, n, d->max_level, d->refine, d->refine_user, err);
+  return forest.build_from_callback(d->root_blocks, n, periodic, d->max_level, d->refine, d->refine_user, err);
 }
 
 int lbm_build_leaves(const lbm_forest_desc* d, int32_t* out, int64_t capacity, int64_t* count) {
@@ -510,6 +520,8 @@ int lbm_create_block_forest(const lbm_forest_desc* d, lbm_forest** out) {
   if ((rc = dev_alloc(f->allocations, &f->d_err, 1))) return rc;
   HIP_TRY(hipMemset(f->d_err, 0, sizeof(int)));
   if ((rc = dev_alloc(f->allocations, &f->d_partials, size_t(kReduceGrid) * 5 * 21))) return rc;
+  if ((rc = dev_alloc(f->allocations, &f->d_check, 3))) return rc;
+  HIP_TRY(hipMemset(f->d_check, 0, 3 * sizeof(unsigned long long)));
   HIP_TRY(hipDeviceSynchronize());
   *out = f.release();
   g_err.clear();
@@ -644,6 +656,28 @@ int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
   (void)hipFree(d_rho);
   (void)hipFree(d_u);
   return rc;
+}
+
+int lbm_set_coalescence_check(lbm_forest* f, int on) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  f->coal_check = on != 0;
+  invalidate_graphs(f);
+  return LBM_OK;
+}
+
+int lbm_coalescence_check(lbm_forest* f, double out[3]) {
+  if (!f || !out) return fail(LBM_E_INVALID, "null pointer");
+  HIP_TRY(hipSetDevice(f->device));
+  unsigned long long h[3];
+  HIP_TRY(hipMemcpyAsync(h, f->d_check, sizeof h, hipMemcpyDeviceToHost, f->stream));
+  HIP_TRY(hipMemsetAsync(f->d_check, 0, sizeof h, f->stream));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  double v[2];
+  std::memcpy(v, h, sizeof v);
+  out[0] = v[0];
+  out[1] = v[1];
+  out[2] = double(h[2]);
+  return LBM_OK;
 }
 
 int lbm_set_schedule(lbm_forest* f, int schedule) {

@@ -27,6 +27,13 @@ bool Forest::is_leaf(int level, int x, int y, int z) const {
   return leaves_.count(block_key(level, x, y, z)) != 0;
 }
 
+bool Forest::outside(int level, int x, int y, int z) const {
+  const int p[3] = {x, y, z};
+  for (int a = 0; a < 3; ++a)
+    if (!periodic[a] && (p[a] < 0 || p[a] >= dims(level, a))) return true;
+  return false;
+}
+
 int Forest::covering_level(int level, int x, int y, int z) const {
   x = wrap(x, dims(level, 0));
   y = wrap(y, dims(level, 1));
@@ -71,6 +78,7 @@ void Forest::enforce_balance() {
         for (int dy = -1; dy <= 1; ++dy)
           for (int dx = -1; dx <= 1; ++dx) {
             if (!dx && !dy && !dz) continue;
+            if (outside(L, l.x + dx, l.y + dy, l.z + dz)) continue;
             const int px = wrap(l.x + dx, dims(L, 0)), py = wrap(l.y + dy, dims(L, 1)),
                       pz = wrap(l.z + dz, dims(L, 2));
             for (;;) {
@@ -91,6 +99,7 @@ bool Forest::balanced() const {
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
           if (!dx && !dy && !dz) continue;
+          if (outside(l.level, l.x + dx, l.y + dy, l.z + dz)) continue;
           if (covering_level(l.level, l.x + dx, l.y + dy, l.z + dz) < l.level - 1) return false;
         }
   }
@@ -147,9 +156,9 @@ void Forest::finalize() {
     });
 }
 
-int Forest::build_from_leaves(const int R_[3], int n_, const int32_t* leaves, int64_t count, bool balance,
-                              std::string& err) {
-  for (int a = 0; a < 3; ++a) R[a] = R_[a];
+int Forest::build_from_leaves(const int R_[3], int n_, const bool periodic_[3], const int32_t* leaves, int64_t count,
+                              bool balance, std::string& err) {
+  for (int a = 0; a < 3; ++a) R[a] = R_[a], periodic[a] = periodic_[a];
   n = n_;
   leaves_.clear();
   for (int64_t i = 0; i < count; ++i) {
@@ -175,9 +184,9 @@ int Forest::build_from_leaves(const int R_[3], int n_, const int32_t* leaves, in
   return LBM_OK;
 }
 
-int Forest::build_from_callback(const int R_[3], int n_, int max_level_, int (*refine)(int, int, int, int, void*),
-                                void* user, std::string& err) {
-  for (int a = 0; a < 3; ++a) R[a] = R_[a];
+int Forest::build_from_callback(const int R_[3], int n_, const bool periodic_[3], int max_level_,
+                                int (*refine)(int, int, int, int, void*), void* user, std::string& err) {
+  for (int a = 0; a < 3; ++a) R[a] = R_[a], periodic[a] = periodic_[a];
   n = n_;
   leaves_.clear();
   std::vector<Leaf> cur;
@@ -210,7 +219,7 @@ int Forest::regrid(const int8_t* flags, int64_t count, int max_level_, Forest& o
     return LBM_E_INVALID;
   }
   out = Forest();
-  for (int a = 0; a < 3; ++a) out.R[a] = R[a];
+  for (int a = 0; a < 3; ++a) out.R[a] = R[a], out.periodic[a] = periodic[a];
   out.n = n;
   out.leaves_ = leaves_;
   std::unordered_set<uint64_t> coarsen;
@@ -246,6 +255,7 @@ int Forest::regrid(const int8_t* flags, int64_t count, int max_level_, Forest& o
         if (d == 13) continue;
         // a leaf finer than L touching the parent's region forbids the merge
         const int qx = p.x + d % 3 - 1, qy = p.y + (d / 3) % 3 - 1, qz = p.z + d / 9 - 1;
+        if (out.outside(L - 1, qx, qy, qz)) continue;
         const int cl = out.covering_level(L - 1, qx, qy, qz);
         if (cl > L - 1) {
           // the neighbour position is split: look at its children next to p
@@ -327,6 +337,11 @@ int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>
       const Leaf& l = leaves[s];
       uint32_t fl = kAllSameLevel;
       for (int d = 0; d < 27; ++d) {
+        if (f.outside(L, l.x + d % 3 - 1, l.y + (d / 3) % 3 - 1, l.z + d / 9 - 1)) {
+          t.nbr[size_t(s) * 27 + d] = kNbrWall;
+          fl &= ~uint32_t(kAllSameLevel);
+          continue;
+        }
         const int px = wrap(l.x + d % 3 - 1, f.dims(L, 0)), py = wrap(l.y + (d / 3) % 3 - 1, f.dims(L, 1)),
                   pz = wrap(l.z + d / 9 - 1, f.dims(L, 2));
         const int cl = f.covering_level(L, px, py, pz);
@@ -361,6 +376,10 @@ int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>
         for (int o = 0; o < 8; ++o) {
           const int vx = 2 * l.x + (o & 1), vy = 2 * l.y + ((o >> 1) & 1), vz = 2 * l.z + (o >> 2);
           for (int d = 0; d < 27; ++d) {
+            if (f.outside(L + 1, vx + d % 3 - 1, vy + (d / 3) % 3 - 1, vz + d / 9 - 1)) {
+              t.fine_nbr[(size_t(row) * 8 + o) * 27 + d] = kFineWall;
+              continue;
+            }
             const int px = wrap(vx + d % 3 - 1, f.dims(L + 1, 0)), py = wrap(vy + (d / 3) % 3 - 1, f.dims(L + 1, 1)),
                       pz = wrap(vz + d / 9 - 1, f.dims(L + 1, 2));
             t.fine_nbr[(size_t(row) * 8 + o) * 27 + d] = maps[L + 1].find(L + 1, px, py, pz);

@@ -1,8 +1,10 @@
 // Host-side forest of octrees and the per-level device tables derived from it.
 //
-// Section 3.2 / 3.3: uniform periodic root grid, 8-way splits chosen by a
-// callback or given as an explicit leaf list, 2:1 balance over face, edge
-// and corner neighbours.  Section 4: every block holds n^3 cells.
+// Section 3.2 / 3.3: uniform root grid, 8-way splits chosen by a callback
+// or given as an explicit leaf list, 2:1 balance over face, edge and corner
+// neighbours.  Section 4: every block holds n^3 cells.  Each axis is
+// periodic or ends in no-slip walls (section 2.2); positions beyond a wall
+// are no neighbours.
 //
 // Device-side view of one level L: slots [0, nblocks) are the level-L leaves
 // in canonical (Morton) order; a level buffer is block-major,
@@ -21,6 +23,7 @@
 namespace lbm {
 
 constexpr int kNbrSelf = 13;        // index of offset (0,0,0) in the 27-entry table
+constexpr int32_t kNbrWall = -1;    // beyond a non-periodic end of the domain: no-slip wall
 constexpr int32_t kNbrFine = -2;    // region of level L+1: values come by coalescence
 constexpr int32_t kNbrCoarse0 = -3; // region of level L-1: entry = kNbrCoarse0 - (pslot * 8 + octant),
                                     // pslot = parent leaf's slot on level L-1, octant = the
@@ -43,16 +46,20 @@ class Forest {
   int R[3] = {1, 1, 1};
   int n = 16;
   int max_level = 0;  // deepest level present
+  bool periodic[3] = {true, true, true};
 
   // Build from an explicit leaf list (validated) or from a refine callback.
   // Returns 0 or an LBM_E_* code with `err` set.
-  int build_from_leaves(const int R_[3], int n_, const int32_t* leaves, int64_t count, bool balance,
-                        std::string& err);
-  int build_from_callback(const int R_[3], int n_, int max_level_, int (*refine)(int, int, int, int, void*),
-                          void* user, std::string& err);
+  int build_from_leaves(const int R_[3], int n_, const bool periodic_[3], const int32_t* leaves, int64_t count,
+                        bool balance, std::string& err);
+  int build_from_callback(const int R_[3], int n_, const bool periodic_[3], int max_level_,
+                          int (*refine)(int, int, int, int, void*), void* user, std::string& err);
 
-  // Level of the leaf covering block position p of `level` (wrapped), if
-  // that leaf is on `level` or coarser; level + 1 if p is split further.
+  // Whether block position p of `level` lies beyond a non-periodic end.
+  bool outside(int level, int x, int y, int z) const;
+  // Level of the leaf covering block position p of `level` (wrapped along
+  // periodic axes; p must not be outside()), if that leaf is on `level` or
+  // coarser; level + 1 if p is split further.
   int covering_level(int level, int x, int y, int z) const;
   bool is_leaf(int level, int x, int y, int z) const;
   int dims(int level, int axis) const { return R[axis] << level; }
@@ -78,6 +85,8 @@ class Forest {
   void finalize();
 };
 
+constexpr int32_t kFineWall = -2;  // fine_nbr entry beyond a non-periodic end
+
 // Tables of one level, ready to copy to the device.
 constexpr int kCoalChunk = 256;  // coalesced pairs per chunk (one workgroup of the coalescence, a pair per thread)
 
@@ -91,7 +100,9 @@ struct LevelTables {
   std::vector<uint32_t> flags;        // [slot]
   std::vector<int32_t> fine_index;    // [slot]: row of fine_nbr, or -1 without a finer neighbour
   std::vector<int32_t> fine_nbr;      // [row][octant][27]: level-(L+1) slot of the block at offset d
-                                      // from the virtual level-(L+1) block (2 b + octant), or -1
+                                      // from the virtual level-(L+1) block (2 b + octant), -1 if
+                                      // that position is no level-(L+1) block, kFineWall beyond a
+                                      // non-periodic end
   std::vector<int32_t> work;          // slot * tiles_per_block + tile
   std::vector<int32_t> fine_slot;     // [row]: the slot whose fine_nbr row it is
   std::vector<uint32_t> coal_pairs;   // coalesced (cell, direction) pairs by fine_nbr row:

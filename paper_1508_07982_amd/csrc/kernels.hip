@@ -7,6 +7,7 @@
 
 #include <type_traits>
 
+#include "forest.hpp"
 #include "kernels.hpp"
 #include "lattice.hpp"
 
@@ -189,6 +190,67 @@ __device__ __forceinline__ int nb_side(int c) {
 // (eq. ftoc, Algorithm 1).  Children are summed in (z, y, x) order.
 constexpr int kCoalThreads = 256;
 
+// floor(d / 2) for d >= -1
+__device__ __forceinline__ int half_floor(int d) { return d < 0 ? -1 : d >> 1; }
+
+// Address of direction a of level-L cell (px, py, pz): local coordinates of
+// the coarse block whose table is nbs (entry 13 is the block itself), at
+// most one cell beyond it (then the neighbour block from the table, which
+// must be a level-L block: a child's two-substep back-trace stays within the
+// coarse cells next to X).
+template <typename S, int N>
+__device__ __forceinline__ const S* coarse_cell(const CoalArgs& c, const int32_t* nbs, int px, int py, int pz, int a) {
+  const int nb = nbs[13 + nb_side<N>(px) + 3 * nb_side<N>(py) + 9 * nb_side<N>(pz)];
+  if (nb < 0) {
+    atomicOr(c.err, kErrNoSource);
+    return static_cast<const S*>(c.cur);
+  }
+  return static_cast<const S*>(c.cur) +
+         pdf_index<N>(a, uint32_t(nb), uint32_t((px & (N - 1)) + N * ((py & (N - 1)) + N * (pz & (N - 1)))));
+}
+
+// Accumulation check of one coalesced pair (see CoalArgs::check): the same
+// 8 values summed in FP64, compared with the compute-type sum.  Recursive
+// summation of 8 terms in a type of unit roundoff u errs by at most
+// gamma_7 sum |v|, gamma_7 = 7u / (1 - 7u) (Higham, Accuracy and Stability
+// of Numerical Algorithms, 2002, eq. (4.4)); the ratio to that bound must
+// not exceed 1.
+struct CheckAcc {
+  double dev = 0.0, ratio = 0.0, count = 0.0;
+};
+template <typename C>
+__device__ __forceinline__ void check_sum(CheckAcc& acc, const C* v, const bool* fine, C regular, C sum) {
+  double s = 0.0, a = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double x = double(fine[q] ? v[q] : regular);
+    s += x;
+    a += fabs(x);
+  }
+  const double u = sizeof(C) == 8 ? 0x1p-53 : 0x1p-24;
+  const double gamma7 = 7.0 * u / (1.0 - 7.0 * u);
+  const double dev = fabs(double(sum) - s);
+  acc.dev = fmax(acc.dev, 0.125 * dev);
+  acc.ratio = fmax(acc.ratio, a > 0.0 ? dev / (gamma7 * a) : 0.0);
+  acc.count += 1.0;
+}
+// Wavefront reduction of the per-lane figures, then one set of atomics per
+// wavefront (non-negative doubles order like their bit patterns, so the
+// maxima are kept with integer atomics).  Every lane of the wave calls it.
+__device__ __forceinline__ void check_flush(unsigned long long* out, CheckAcc acc) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.dev = fmax(acc.dev, __shfl_xor(acc.dev, off, 64));
+    acc.ratio = fmax(acc.ratio, __shfl_xor(acc.ratio, off, 64));
+    acc.count += __shfl_xor(acc.count, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, (unsigned long long)__double_as_longlong(acc.dev));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(acc.ratio));
+    atomicAdd(out + 2, (unsigned long long)acc.count);
+  }
+}
+
 template <typename S, int N>
 __global__ void __launch_bounds__(kCoalThreads) coalesce_kernel(CoalArgs c) {
   using C = typename Form<S>::C;
@@ -200,6 +262,7 @@ __global__ void __launch_bounds__(kCoalThreads) coalesce_kernel(CoalArgs c) {
   for (int q = threadIdx.x; q < 8 * 27; q += blockDim.x) fns[q] = c.fine_nbr[int64_t(row) * 216 + q];
   for (int q = threadIdx.x; q < 27; q += blockDim.x) nbs[q] = c.nbr[int64_t(slot) * 27 + q];
   __syncthreads();
+  CheckAcc acc;
   for (int t = first + int(threadIdx.x); t < end; t += blockDim.x) {
     const uint32_t w = c.pairs[t];
     const int A = int(w >> 16), cell = int(w & 0xFFFFu);
@@ -217,37 +280,59 @@ __global__ void __launch_bounds__(kCoalThreads) coalesce_kernel(CoalArgs c) {
     // a fine value at the x face it leaves through comes from the x-face copy
     const int xout = EX < 0 ? 0 : N - 1;
     const bool xcopy = EX != 0;
+    const int Ab = opp(A);
     C v[8];
-    bool fine[8];
+    bool fine[8];  // false: the child's value is X's regular source value
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int yx = cx + (q & 1) - EX, yy = cy + ((q >> 1) & 1) - EY, yz = cz + (q >> 2) - EZ;
+      const int ox = q & 1, oy = (q >> 1) & 1, oz = q >> 2;
+      const int yx = cx + ox - EX, yy = cy + oy - EY, yz = cz + oz - EZ;
       const int fy = fn[13 + nb_side<N>(yx) + 3 * nb_side<N>(yy) + 9 * nb_side<N>(yz)];
       const int zx = yx - EX, zy = yy - EY, zz = yz - EZ;
       const int fz = fn[13 + nb_side<N>(zx) + 3 * nb_side<N>(zy) + 9 * nb_side<N>(zz)];
       const S* p = static_cast<const S*>(c.cur);
+      bool own = true;
       if (fy >= 0) {
         const int lx = yx & (N - 1), jk = (yy & (N - 1)) + N * (yz & (N - 1));
         p = xcopy && lx == xout ? static_cast<const S*>(c.fine1_x) + xface_index_rt<N>(A, uint32_t(fy), uint32_t(jk))
                                 : static_cast<const S*>(c.fine1) + pdf_index<N>(A, uint32_t(fy), uint32_t(lx + N * jk));
+      } else if (fy == kFineWall) {
+        // c - e_A is a wall: c bounced back its own value of direction Ab
+        // after the first substep, which it had pulled from w = c + e_A at t
+        // (the fine state there, or the exploded value of w's parent)
+        const int wx = cx + ox + EX, wy = cy + oy + EY, wz = cz + oz + EZ;
+        const int fw = fn[13 + nb_side<N>(wx) + 3 * nb_side<N>(wy) + 9 * nb_side<N>(wz)];
+        p = fw >= 0 ? static_cast<const S*>(c.fine0) +
+                          pdf_index<N>(Ab, uint32_t(fw), uint32_t((wx & (N - 1)) + N * ((wy & (N - 1)) + N * (wz & (N - 1)))))
+                    : coarse_cell<S, N>(c, nbs, i + half_floor(ox + EX), j + half_floor(oy + EY),
+                                        k + half_floor(oz + EZ), Ab);
       } else if (fz >= 0) {
         const int lx = zx & (N - 1), jk = (zy & (N - 1)) + N * (zz & (N - 1));
         p = xcopy && lx == xout ? static_cast<const S*>(c.fine0_x) + xface_index_rt<N>(A, uint32_t(fz), uint32_t(jk))
                                 : static_cast<const S*>(c.fine0) + pdf_index<N>(A, uint32_t(fz), uint32_t(lx + N * jk));
+      } else if (fz == kFineWall) {
+        // y = c - e_A bounced back at the wall in the first substep: its
+        // exploded value of direction Ab, the value of y's parent
+        p = coarse_cell<S, N>(c, nbs, i + half_floor(ox - EX), j + half_floor(oy - EY), k + half_floor(oz - EZ),
+                              Ab);
+      } else {
+        own = false;
       }
-      fine[q] = fy >= 0 || fz >= 0;
+      fine[q] = own;
       v[q] = Form<S>::ld(p);
     }
     const C regular = nb >= 0 ? C(Form<S>::ld(rp)) : C(0);
     C sum = C(0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) sum += fine[q] ? v[q] : regular;
+    if (c.check) check_sum<C>(acc, v, fine, regular, sum);
     // a pair entering through an x face goes to the x-face layout
     S* o = EX != 0 && i == (EX > 0 ? 0 : N - 1)
                ? static_cast<S*>(c.out_x) + xface_index_rt<N>(A, uint32_t(row), uint32_t(j + N * k))
                : static_cast<S*>(c.out) + pdf_index<N>(A, uint32_t(row), uint32_t(cell));
     Form<S>::st(o, sum * C(0.125));
   }
+  if (c.check) check_flush(c.check, acc);
 }
 
 // x-face copy of a buffer (see CoalArgs): one thread per element of xf.

@@ -46,7 +46,8 @@ enum ErrBits : int { kErrNoSource = 1, kErrNoChild = 2 };
 // Coalescence of level L for one of its substeps (eq. ftoc), run after the
 // finer level's two substeps and before the level-L sweep: for every
 // coalesced pair (X, a) of a slot with finer neighbours, the mean over the 8
-// children of X of what the finer level's second stream pulled into them,
+// children of X of what the finer level's second stream pulled into them
+// (with the bounce-back at no-slip walls in the fine ghost layers),
 // written to out[row][a][cell] (block-major like the state, one block per
 // fine_nbr row), or to out_x for a pair that enters through an x face
 // (cell x = 0 with e_a,x = +1, x = n - 1 with e_a,x = -1; x-face layout).
@@ -73,6 +74,13 @@ struct CoalArgs {
   const int32_t* nbr;         // level-L [slot][27]
   const int32_t* fine_nbr;    // [row][8][27]
   const int32_t* fine_slot;   // [row]
+  // accumulation check (null: off): each pair's 8-child sum is also formed
+  // in FP64 from the same loaded values; check[0] and check[1] keep, as the
+  // bit patterns of non-negative doubles, the largest |compute-type mean -
+  // FP64 mean| and the largest ratio of |sum - FP64 sum| to the bound
+  // gamma_7 sum |v| of recursive summation of 8 terms; check[2] counts pairs
+  unsigned long long* check;
+  int* err;                   // error bits (table lookup failures)
 };
 
 hipError_t launch_coalesce(int storage, int n, const CoalArgs& a, hipStream_t stream);

@@ -22,6 +22,15 @@ __host__ __device__ __forceinline__ constexpr int ey(int a) {
 __host__ __device__ __forceinline__ constexpr int ez(int a) {
   return a == 5 || a == 11 || a == 14 || a == 15 || a == 18 ? 1 : (a == 6 || a == 12 || a == 13 || a == 16 || a == 17 ? -1 : 0);
 }
+// the opposite direction: pairs (a, a + 1) for odd a
+__host__ __device__ __forceinline__ constexpr int opp(int a) { return a == 0 ? 0 : (a & 1 ? a + 1 : a - 1); }
+constexpr bool opp_is_opposite() {
+  for (int a = 0; a < 19; ++a)
+    if (ex(opp(a)) != -ex(a) || ey(opp(a)) != -ey(a) || ez(opp(a)) != -ez(a)) return false;
+  return true;
+}
+static_assert(opp_is_opposite(), "opposite directions");
+
 template <typename C>
 __host__ __device__ __forceinline__ constexpr C wgt(int a) {
   return a == 0 ? C(1) / C(3) : (a <= 6 ? C(1) / C(18) : C(1) / C(36));

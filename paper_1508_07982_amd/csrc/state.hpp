@@ -81,6 +81,8 @@ struct lbm_forest {
   double accel0[3] = {0.0, 0.0, 0.0};  // lattice acceleration of level 0
   std::map<std::vector<int>, hipGraphExec_t> graphs;
   int* d_err = nullptr;
+  bool coal_check = false;                  // FP64 accumulation check of the coalescence
+  unsigned long long* d_check = nullptr;    // its figures (see CoalArgs::check)
   double* d_partials = nullptr;
   std::vector<void*> allocations;
 

@@ -108,22 +108,30 @@ __device__ __forceinline__ const S* parent_ptr(const SweepArgs& a, int code, int
   return static_cast<const S*>(a.par) + pdf_index<N>(A, uint32_t(pp >> 3), uint32_t(px + N * (py + N * pz)));
 }
 
-// Special sources of cell (i, j, k), direction A.
+// Special sources of cell x = (i, j, k) of block `slot`, direction A.
 //
+// No-slip wall (x - e_A lies beyond a non-periodic end, section 2.2): the
+// boundary cell holds what x sent towards it, reversed -- x's own value of
+// the opposite direction in the state being streamed (halfway bounce-back).
 // Coarse source (the cell x - e_A lies in a level-(L-1) leaf):
 //   substep 1: the exploded parent value of x - e_A;
 //   substep 2: x - e_A is a halo cell whose first-substep value was pulled
-//   from x - 2 e_A: the level's own state at t there, or the exploded parent
-//   value if x - 2 e_A is also in the coarse region.
+//   from x - 2 e_A: the level's own state at t there, the exploded parent
+//   value if x - 2 e_A is also in the coarse region, or, if x - 2 e_A is a
+//   wall, the halo cell's own bounced-back value: its exploded parent value
+//   of the opposite direction (ghost layers get the boundary treatment too,
+//   section 4.1).
 // coarse_source returns its address (an inconsistent table sets an error
 // bit and yields an in-bounds dummy address), so that the loads of all
 // cells of a lane can be issued together.
 template <typename S, int N, int A>
-__device__ __forceinline__ const S* coarse_source(const SweepArgs& a, const SlotCache& sc, int i, int j, int k) {
+__device__ __forceinline__ const S* coarse_source(const SweepArgs& a, const SlotCache& sc, int slot, int i, int j,
+                                                  int k) {
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
   const S* dummy = static_cast<const S*>(a.cur);
   const int sx = i - EX, sy = j - EY, sz = k - EZ;
   const int code = pick<-EX, -EY, -EZ>(sc, outside<N>(sx), outside<N>(sy), outside<N>(sz));
+  if (code == kNbrWall) return static_cast<const S*>(a.cur) + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(i + N * (j + N * k)));
   if (code > kNbrCoarse0) {  // not a coarse region: never expected here
     atomicOr(a.err, kErrNoSource);
     return dummy;
@@ -134,6 +142,7 @@ __device__ __forceinline__ const S* coarse_source(const SweepArgs& a, const Slot
   if (cz >= 0)
     return static_cast<const S*>(a.prev) +
            pdf_index<N>(A, uint32_t(cz), uint32_t((zx & (N - 1)) + N * ((zy & (N - 1)) + N * (zz & (N - 1)))));
+  if (cz == kNbrWall) return parent_ptr<S, N, opp(A)>(a, code, sx & (N - 1), sy & (N - 1), sz & (N - 1));
   if (cz > kNbrCoarse0) {
     atomicOr(a.err, kErrNoSource);
     return dummy;
@@ -292,7 +301,7 @@ __device__ __forceinline__ uint32_t special_cells(NbrMasks m, uint32_t fl, int i
 // and coalesced pairs), addressed first and loaded together: one memory
 // round trip per direction.
 template <typename S, int N, int A = 0>
-__device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, const NbrMasks& m, uint32_t fl, int i0,
+__device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, int slot, const NbrMasks& m, uint32_t fl, int i0,
                                        int j, int k, typename Form<S>::C (*h)[Geo<S, N>::W]) {
   using C = typename Form<S>::C;
   constexpr int W = Geo<S, N>::W;
@@ -304,14 +313,14 @@ __device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, 
     for (int c = 0; c < W; ++c) {
       const S* p = !((spec >> c) & 1u) ? static_cast<const S*>(a.cur)
                    : (co >> c) & 1u    ? coalesced_source<S, N, A>(a, sc, i0 + c, j, k)
-                                       : coarse_source<S, N, A>(a, sc, i0 + c, j, k);
+                                       : coarse_source<S, N, A>(a, sc, slot, i0 + c, j, k);
       v[c] = Form<S>::ld(p);
     }
 #pragma unroll
     for (int c = 0; c < W; ++c)
       if ((spec >> c) & 1u) h[A][c] = v[c];
   }
-  if constexpr (A + 1 < 19) fixups<S, N, A + 1>(a, sc, m, fl, i0, j, k, h);
+  if constexpr (A + 1 < 19) fixups<S, N, A + 1>(a, sc, slot, m, fl, i0, j, k, h);
 }
 
 // Relaxation of the opposite pair (A, A + 1), e_{A+1} = -e_A: with
@@ -426,7 +435,7 @@ __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache&
   C h[19][W];
   uint32_t odd = 0;
   pull_all<S, N, SIMPLE>(a, sc, slot, i0, j, k, h, odd);
-  if (!SIMPLE && odd) fixups<S, N>(a, sc, nbr_masks(sc), fl, i0, j, k, h);
+  if (!SIMPLE && odd) fixups<S, N>(a, sc, slot, nbr_masks(sc), fl, i0, j, k, h);
   if (a.collide) {
 #pragma unroll
     for (int c = 0; c < W; ++c) collide_cell<S, TRT>(a, h, c);
@@ -518,7 +527,7 @@ __device__ __forceinline__ void set_half(uint32_t& w, int hi, float v) {
 }
 
 template <int N, int A = 0>
-__device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& sc, const NbrMasks& m, uint32_t fl,
+__device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& sc, int slot, const NbrMasks& m, uint32_t fl,
                                           int i0, int j, int k, uint32_t (*q)[4]) {
   uint32_t co;
   const uint32_t spec = special_cells<N, 8, A>(m, fl, i0, j, k, co);
@@ -528,14 +537,14 @@ __device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& s
     for (int c = 0; c < 8; ++c) {
       const __half* p = !((spec >> c) & 1u) ? static_cast<const __half*>(a.cur)
                         : (co >> c) & 1u    ? coalesced_source<__half, N, A>(a, sc, i0 + c, j, k)
-                                            : coarse_source<__half, N, A>(a, sc, i0 + c, j, k);
+                                            : coarse_source<__half, N, A>(a, sc, slot, i0 + c, j, k);
       v[c] = Form<__half>::ld(p);
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c)
       if ((spec >> c) & 1u) set_half(q[A][c >> 1], c & 1, v[c]);
   }
-  if constexpr (A + 1 < 19) fixups_h8<N, A + 1>(a, sc, m, fl, i0, j, k, q);
+  if constexpr (A + 1 < 19) fixups_h8<N, A + 1>(a, sc, slot, m, fl, i0, j, k, q);
 }
 
 // store_face_side for the packed lane: cell 0 is the low half of register
@@ -558,7 +567,7 @@ __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCac
   uint32_t odd = 0;
   issue_all_h8<N, SIMPLE>(a, sc, slot, i0, j, k, q, edge, odd);
   shift_all_h8<N>(i0, q, edge);
-  if (!SIMPLE && odd) fixups_h8<N>(a, sc, nbr_masks(sc), fl, i0, j, k, q);
+  if (!SIMPLE && odd) fixups_h8<N>(a, sc, slot, nbr_masks(sc), fl, i0, j, k, q);
   if (a.collide) {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {

@@ -41,6 +41,7 @@ class ForestDesc(ctypes.Structure):
         ("root_blocks", ctypes.c_int * 3),
         ("cells_per_block", ctypes.c_int),
         ("max_level", ctypes.c_int),
+        ("periodic", ctypes.c_int * 3),
         ("leaves", ctypes.POINTER(ctypes.c_int32)),
         ("num_leaves", ctypes.c_int64),
         ("refine", REFINE_FN),
@@ -72,6 +73,8 @@ _SIGNATURES = {
     "lbm_get_moments_static": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_mass": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
     "lbm_set_schedule": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_set_coalescence_check": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_coalescence_check": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_launch": [ctypes.c_void_p, ctypes.c_int],
     "lbm_synchronize": [ctypes.c_void_p],
     "lbm_time_sweeps": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
@@ -144,11 +147,12 @@ def lattice():
     return e, w
 
 
-def _make_desc(roots, n, max_level, leaves, refine, balance, storage, device, stream):
+def _make_desc(roots, n, max_level, leaves, refine, balance, storage, device, stream, periodic=(True, True, True)):
     d = ForestDesc()
     roots = (roots,) * 3 if np.isscalar(roots) else tuple(roots)
     for a in range(3):
         d.root_blocks[a] = int(roots[a])
+        d.periodic[a] = int(periodic[a])
     d.cells_per_block = int(n)
     d.max_level = int(max_level)
     keep = []
@@ -168,9 +172,10 @@ def _make_desc(roots, n, max_level, leaves, refine, balance, storage, device, st
     return d, keep
 
 
-def build_leaves(roots, n, max_level, leaves=None, refine=None, balance=True) -> np.ndarray:
+def build_leaves(roots, n, max_level, leaves=None, refine=None, balance=True,
+                 periodic=(True, True, True)) -> np.ndarray:
     """Host-only: the library's balanced forest, canonical leaf list (N, 4)."""
-    d, keep = _make_desc(roots, n, max_level, leaves, refine, balance, "f32", 0, None)
+    d, keep = _make_desc(roots, n, max_level, leaves, refine, balance, "f32", 0, None, periodic)
     count = ctypes.c_int64(0)
     _check(load_library().lbm_build_leaves(ctypes.byref(d), None, 0, ctypes.byref(count)))
     out = np.zeros((count.value, 4), dtype=np.int32)
@@ -179,9 +184,10 @@ def build_leaves(roots, n, max_level, leaves=None, refine=None, balance=True) ->
     return out
 
 
-def plan_level_stats(roots, n, max_level, level, leaves=None, refine=None, balance=True, storage="f32") -> dict:
+def plan_level_stats(roots, n, max_level, level, leaves=None, refine=None, balance=True, storage="f32",
+                     periodic=(True, True, True)) -> dict:
     """Host-only: layout figures of one level of the forest the library would build."""
-    d, keep = _make_desc(roots, n, max_level, leaves, refine, balance, storage, 0, None)
+    d, keep = _make_desc(roots, n, max_level, leaves, refine, balance, storage, 0, None, periodic)
     out = np.zeros(8, dtype=np.int64)
     _check(load_library().lbm_plan_level_stats(ctypes.byref(d), int(level), _ptr(out)))
     del keep
@@ -198,11 +204,13 @@ class Forest:
     """A refined LBM simulation owned by the HIP library."""
 
     def __init__(self, roots, n, max_level, leaves=None, refine=None, balance=True, storage="f32",
-                 device=0, stream=None):
+                 device=0, stream=None, periodic=(True, True, True)):
+        """periodic: per axis, True for a periodic axis, False for no-slip
+        walls at both ends (section 2.2)."""
         self._lib = load_library()
         self.storage = storage
         self.n = int(n)
-        d, keep = _make_desc(roots, n, max_level, leaves, refine, balance, storage, device, stream)
+        d, keep = _make_desc(roots, n, max_level, leaves, refine, balance, storage, device, stream, periodic)
         h = ctypes.c_void_p()
         _check(self._lib.lbm_create_block_forest(ctypes.byref(d), ctypes.byref(h)))
         del keep
@@ -271,6 +279,15 @@ class Forest:
 
     def set_schedule(self, schedule: str):
         _check(self._lib.lbm_set_schedule(self._h, SCHEDULE[schedule]))
+
+    def set_coalescence_check(self, on: bool = True):
+        _check(self._lib.lbm_set_coalescence_check(self._h, int(bool(on))))
+
+    def coalescence_check(self) -> dict:
+        """FP64 accumulation-check figures since the last call (reset)."""
+        out = np.zeros(3)
+        _check(self._lib.lbm_coalescence_check(self._h, _ptr(out)))
+        return {"max_abs_dev": float(out[0]), "max_bound_ratio": float(out[1]), "pairs": int(out[2])}
 
     def set_launch(self, persistent: int):
         _check(self._lib.lbm_set_launch(self._h, int(persistent)))
