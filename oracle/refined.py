@@ -33,6 +33,9 @@ class _Level(ctypes.Structure):
         ("trt", ctypes.c_int),
         ("lambda_o", ctypes.c_double),
         ("accel", ctypes.c_double * 3),
+        ("interp", ctypes.c_int),
+        ("expl_oct", ctypes.c_void_p),
+        ("expl_nbr", ctypes.c_void_p),
     ]
 
 
@@ -45,6 +48,7 @@ def _load():
         path = _build.build(force=False)
         lib = ctypes.CDLL(path)
         lib.orc_coarse_steps.argtypes = [ctypes.POINTER(_Level), ctypes.c_int, ctypes.c_int]
+        lib.orc_explode.argtypes = [ctypes.POINTER(_Level), ctypes.c_int]
         for name in ("orc_equilibrium", "orc_moments"):
             getattr(lib, name).argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_collide.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_double]
@@ -134,11 +138,14 @@ class RefinedOracle:
     """FP64 Algorithm-1 oracle on a 2:1 balanced forest."""
 
     def __init__(self, forest: Forest, omega0: float, coalescence: str = "virtual", lambda_eo=None,
-                 accel0=None):
+                 accel0=None, interpolation: bool = False):
         """omega0: SRT omega_0, or with lambda_eo (TRT) the even rate
         lambda_e,0, scaled per level by eq. omega_scaling_0.  lambda_eo: TRT
         with lambda_o,L from eq. lambda_oL; accel0: constant lattice
-        acceleration of level 0 (force term, a_L by eq. force_scaling)."""
+        acceleration of level 0 (force term, a_L by eq. force_scaling).
+        interpolation: explode with the limited linear reconstruction
+        (refined_oracle.c, explode) instead of eq. ctof."""
+        self.interpolation = bool(interpolation)
         self.forest = forest
         self.n = forest.n
         self.num_levels = forest.max_level + 1
@@ -211,6 +218,9 @@ class RefinedOracle:
             lv.trt = int(self.trt)
             lv.lambda_o = self.lambda_o[L]
             lv.accel = (ctypes.c_double * 3)(*self.accel[L])
+            lv.interp = int(self.interpolation)
+            lv.expl_oct = _ptr(t.expl_oct)
+            lv.expl_nbr = _ptr(t.expl_nbr)
         self._levels = arr
 
     def step(self, steps: int = 1):
@@ -218,6 +228,17 @@ class RefinedOracle:
         self._build_levels()
         _load().orc_coarse_steps(self._levels, self.num_levels, int(steps))
         self.steps_done += steps
+
+    def explode(self, L: int):
+        """Only the explosion of level L >= 1 from the current level-(L-1)
+        state: afterwards stored cells [n_int(L), n_store) hold E_L's values."""
+        self._build_levels()
+        _load().orc_explode(self._levels, int(L))
+
+    def exploded(self, L: int):
+        """(coordinates, values) of the explosion cells E_L of level L."""
+        c = self.tables[L].cells
+        return c.coords[c.n_int:], self.F[L][c.n_int:]
 
     def stream_calls(self, reset: bool = True) -> np.ndarray:
         """Stream(L) calls per level since the last reset."""
@@ -232,7 +253,7 @@ class RefinedOracle:
         nf = regrid_forest(self.forest, flags, max_level)
         if self.trt:
             raise NotImplementedError("regrid of a TRT / forced state")
-        new = RefinedOracle(nf, self._omega0, self._coalescence)
+        new = RefinedOracle(nf, self._omega0, self._coalescence, interpolation=self.interpolation)
         pdfs = remap_interior(self.forest, [self.interior_pdfs(L) for L in range(self.num_levels)], nf)
         for L in range(new.num_levels):
             new.F[L][:] = np.nan

@@ -71,6 +71,9 @@ typedef struct {
   int trt;          /* 1: TRT + force collision with the two fields below */
   double lambda_o;  /* TRT odd rate lambda_o,L                          */
   double accel[3];  /* lattice acceleration a_L of this level           */
+  int interp;       /* 1: interpolated explosion (the two tables below)  */
+  const int32_t *expl_oct;  /* n_store - n_int x 3: octant of the cell in its parent */
+  const int32_t *expl_nbr;  /* n_store - n_int x 6: parent's face neighbours in I_{L-1}, -1 none */
 } orc_level;
 
 void orc_lattice(int32_t *e, double *w) {
@@ -154,13 +157,40 @@ static void collide(orc_level *lv) {
     orc_collide(lv->n_int, lv->F, lv->omega);
 }
 
+/* minmod limiter: the smaller one-sided difference if both have the same
+   sign, else 0 */
+static double minmod(double p, double q) {
+  if (p * q <= 0.0) return 0.0;
+  return fabs(p) < fabs(q) ? p : q;
+}
+
+/* Explosion (section 4, eq. ctof): every cell of E_L takes its parent's 19
+   values.  Interpolated form (the interpolation of exploded values of
+   Algorithm 2, section 4.1; the scheme it cites is not given in the paper,
+   so this is a reading): each PDF is reconstructed linearly inside the
+   parent, f_a(x) = f_a(P) + sum_d (o_d - 1/2) / 2 g_d, o the octant of x in
+   P, g_d the minmod-limited slope of f_a along axis d from P's two face
+   neighbours (0 if either is not a level-(L-1) interior cell).  The 8
+   children of a parent average to its values exactly, so mass and momentum
+   are unchanged, and zero slopes give eq. ctof. */
 static void explode(orc_level *lv, const orc_level *coarse) {
   const int64_t m = lv->n_store - lv->n_int;
 #pragma omp parallel for schedule(static)
   for (int64_t e = 0; e < m; ++e) {
     const double *src = coarse->F + Q * (int64_t)lv->expl_src[e];
     double *dst = lv->F + Q * (lv->n_int + e);
-    for (int a = 0; a < Q; ++a) dst[a] = src[a];
+    for (int a = 0; a < Q; ++a) {
+      double v = src[a];
+      if (lv->interp) {
+        for (int d = 0; d < 3; ++d) {
+          const int32_t ip = lv->expl_nbr[6 * e + 2 * d], im = lv->expl_nbr[6 * e + 2 * d + 1];
+          if (ip < 0 || im < 0) continue;
+          const double g = minmod(coarse->F[Q * (int64_t)ip + a] - src[a], src[a] - coarse->F[Q * (int64_t)im + a]);
+          v += (lv->expl_oct[3 * e + d] - 0.5) * 0.5 * g;
+        }
+      }
+      dst[a] = v;
+    }
   }
   if (lv->poison_far) {
     for (int64_t i = lv->n_live; i < lv->n_store; ++i)
@@ -234,6 +264,12 @@ static void step(orc_level *lv, int L, int Lmax) {
 
 void orc_coarse_steps(orc_level *levels, int num_levels, int steps) {
   for (int s = 0; s < steps; ++s) step(levels, 0, num_levels - 1);
+}
+
+/* the explosion of level L >= 1 alone, from the current level-(L-1) state
+   (for tests of the exploded values) */
+void orc_explode(orc_level *levels, int L) {
+  if (L >= 1) explode(&levels[L], &levels[L - 1]);
 }
 
 int orc_sizeof_level(void) { return (int)sizeof(orc_level); }

@@ -11,7 +11,11 @@ Definitions (section 2.3, section 4, section 4.3, section 4.4):
   that are streamed but never collided (section 4: both stream and boundary
   handling include them, collision does not).
 * E_L = {x in region(L-1) : dist_L(x) <= 4}: the four fine ghost layers
-  filled from two coarse layers by the explosion (section 4, section 4.3).
+  filled from two coarse layers by the explosion (section 4, section 4.3):
+  homogeneously, every cell takes its parent's 19 values (eq. ctof), or, as
+  the interpolation of the exploded values that Algorithm 2 adds (section
+  4.1), a limited linear reconstruction of each PDF inside the parent (see
+  refined_oracle.c).
 * Stream (pull form): for x in I_L u H_L and every direction a, the new value
   is the old value at x - e_a.  A source inside region(L+1) has no level-L
   value; such an (x, a) must be in the coalescence set.
@@ -223,15 +227,30 @@ class LevelTables:
             pull[:, a] = idx
         self.pull = pull.astype(np.int32)
 
-        # explosion: parent (in I_{L-1}) of every E_L cell
+        # explosion: parent (in I_{L-1}) of every E_L cell; for the
+        # interpolated explosion also the cell's octant inside its parent and
+        # the parent's 6 face neighbours (+x, -x, +y, -y, +z, -z) in I_{L-1},
+        # -1 where that neighbour is no level-(L-1) interior cell
         far = cells.coords[cells.n_int:]
         if len(far):
-            idx, _ = coarser.lookup(far // 2)
+            par = far // 2
+            idx, _ = coarser.lookup(par)
             if np.any(idx < 0) or np.any(idx >= coarser.n_int):
                 raise AssertionError(f"level {L}: explosion parent not in I_{L-1}")
             self.expl_src = idx.astype(np.int32)
+            self.expl_oct = (far - 2 * par).astype(np.int32)
+            nbr = np.empty((len(far), 6), dtype=np.int64)
+            for d in range(3):
+                for side, sgn in ((0, 1), (1, -1)):
+                    step = np.zeros(3, dtype=np.int64)
+                    step[d] = sgn
+                    q, _ = coarser.lookup(par + step)
+                    nbr[:, 2 * d + side] = np.where((q >= 0) & (q < coarser.n_int), q, -1)
+            self.expl_nbr = nbr.astype(np.int32)
         else:
             self.expl_src = np.zeros(0, dtype=np.int32)
+            self.expl_oct = np.zeros((0, 3), dtype=np.int32)
+            self.expl_nbr = np.zeros((0, 6), dtype=np.int32)
 
         # coalescence pairs
         cc, cd, ch = [], [], []
