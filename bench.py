@@ -290,6 +290,18 @@ def main():
                                         "launch": launch_table(launcht), "mass_drift": abs(Mtb - Mta) / Mta}
         gt.close()
         del gt
+        # the interpolated explosion (limited linear reconstruction of the
+        # exploded values) instead of eq. ctof, FP32
+        gi = make_forest(lbm, W, w, "f32", stream.cuda_stream)
+        gi.set_explosion_interpolation(True)
+        gi.step_coarse(1)
+        msi = timed_steps(torch, gi, stream, 5)
+        swi, coi = gi.time_launches(1)
+        forms["f32_interpolated_explosion_graph"] = {
+            "MLUPS": round(head["updates_per_coarse_step"] / (msi * 1e-3) / 1e6, 1), "ms_per_step": round(msi, 3),
+            "per_level": level_table(gi, swi, 4, coi)}
+        gi.close()
+        del gi
         forms["batching_slab_sphere"] = batching_form(torch, lbm, W, stream)
         gp = make_forest(lbm, W, w, "f32", stream.cuda_stream)
         gp.set_schedule("per_block")

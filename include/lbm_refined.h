@@ -206,6 +206,20 @@ int lbm_get_moments_static(lbm_forest *f, double *rho, double *u);
  * LBM_E_NONFINITE if NaN or Inf appears.  Synchronizes the stream. */
 int lbm_mass(lbm_forest *f, double *mass, double momentum[3]);
 
+/* Interpolated explosion (on != 0; off by default: the homogeneous
+ * explosion of eq. ctof).  Algorithm 2 refines the homogeneous explosion by
+ * an interpolation of the exploded values (section 4.1) whose scheme the
+ * paper only cites; the library's reading: every PDF of a fine ghost cell is
+ * reconstructed linearly inside its coarse parent P, f_a(P) + sum_d
+ * (o_d - 1/2)/2 g_d with o the cell's octant in P and g_d the minmod-limited
+ * slope from P's two face neighbours along axis d (0 where either is not an
+ * interior cell of P's level, a wall included).  The 8 children of a parent
+ * average to its values, so mass and momentum are kept, and zero slopes give
+ * eq. ctof.  It applies to every exploded value the sweeps and the
+ * coalescence read; lbm_regrid still explodes whole new blocks
+ * homogeneously.  Invalidates captured graphs. */
+int lbm_set_explosion_interpolation(lbm_forest *f, int on);
+
 /* FP64 accumulation check of the coalescence (eq. ftoc, section 4.4).  With
  * FP32 or FP16 storage the 8-child sums are formed in FP32; with the check
  * on (on != 0; off by default) every coalescence launch also sums the same

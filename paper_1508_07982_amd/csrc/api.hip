@@ -138,7 +138,7 @@ int make_levels(int n, size_t s, const std::vector<LevelTables>& tabs, std::vect
     if ((rc = upload(v.allocs, &v.fine_slot, t.fine_slot))) return rc;
     if ((rc = upload(v.allocs, &v.pairs, t.coal_pairs))) return rc;
     if ((rc = upload(v.allocs, &v.chunks, t.coal_chunks))) return rc;
-    v.nchunks = int32_t(t.coal_chunks.size() / 3);
+    v.nchunks = int32_t(t.coal_chunks.size() / 4);
     if (v.nchunks) {
       uint8_t* p = nullptr;
       if ((rc = dev_alloc(v.allocs, &p, size_t(t.fine_blocks) * 19 * n3 * s))) return rc;
@@ -243,6 +243,8 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
     a.accel[q] = float(d.accel[q]);
     a.accel64[q] = d.accel[q];
   }
+  a.interp = f->interp ? 1 : 0;
+  a.par_nbr = L > 0 ? f->lv[L - 1].nbr : nullptr;
   if (L + 1 < nlev && d.nchunks > 0) {
     Op c;
     c.level = L;
@@ -263,6 +265,8 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
     c.coal.fine_slot = d.fine_slot;
     c.coal.check = f->coal_check ? f->d_check : nullptr;
     c.coal.err = f->d_err;
+    c.coal.interp = f->interp ? 1 : 0;
+    c.coal.walls = f->forest.periodic[0] && f->forest.periodic[1] && f->forest.periodic[2] ? 0 : 1;
     ops.push_back(c);
   }
   ops.push_back(op);
@@ -656,6 +660,13 @@ int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
   (void)hipFree(d_rho);
   (void)hipFree(d_u);
   return rc;
+}
+
+int lbm_set_explosion_interpolation(lbm_forest* f, int on) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  f->interp = on != 0;
+  invalidate_graphs(f);
+  return LBM_OK;
 }
 
 int lbm_set_coalescence_check(lbm_forest* f, int on) {

@@ -449,6 +449,7 @@ int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>
       const int64_t end = int64_t(t.coal_pairs.size());
       for (int64_t b = first; b < end; b += kCoalChunk) {
         t.coal_chunks.push_back(row);
+        t.coal_chunks.push_back(s);
         t.coal_chunks.push_back(int32_t(b));
         t.coal_chunks.push_back(int32_t(std::min<int64_t>(end, b + kCoalChunk)));
       }

@@ -88,7 +88,13 @@ class Forest {
 constexpr int32_t kFineWall = -2;  // fine_nbr entry beyond a non-periodic end
 
 // Tables of one level, ready to copy to the device.
-constexpr int kCoalChunk = 256;  // coalesced pairs per chunk (one workgroup of the coalescence, a pair per thread)
+// Coalesced pairs per thread of the coalescence launch, and per chunk (one
+// workgroup of 256 threads).  The launch is latency-bound (a chain of
+// dependent loads per workgroup); on the benchmark grids 1 pair per thread
+// ran fastest (level 2 of the sphere shell: 47 us per launch, against 50 us
+// with 2 and 67 us with 4 pairs per thread in FP32).
+constexpr int kCoalPairs = 1;
+constexpr int kCoalChunk = 256;
 
 struct LevelTables {
   int level = 0;
@@ -107,8 +113,8 @@ struct LevelTables {
   std::vector<int32_t> fine_slot;     // [row]: the slot whose fine_nbr row it is
   std::vector<uint32_t> coal_pairs;   // coalesced (cell, direction) pairs by fine_nbr row:
                                       // (direction << 16) | cell
-  std::vector<int32_t> coal_chunks;   // [chunk][3]: fine_nbr row, first pair, end pair (at most
-                                      // kCoalChunk pairs of one row each)
+  std::vector<int32_t> coal_chunks;   // [chunk][4]: fine_nbr row, slot, first pair, end pair (at
+                                      // most kCoalChunk pairs of one row each)
   int64_t coarse_blocks = 0;          // blocks touching level L-1
   int64_t fine_blocks = 0;            // blocks touching level L+1
   int64_t coalesced_pairs = 0;

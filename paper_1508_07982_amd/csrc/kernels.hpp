@@ -39,6 +39,8 @@ struct SweepArgs {
   double lambda_o64;          // lambda_o,L (FP64 form)
   float accel[3];             // lattice acceleration a_L (FP32 arithmetic forms)
   double accel64[3];          // a_L (FP64 form)
+  int32_t interp;             // 1: interpolated explosion (see interp_value in lattice.hpp)
+  const int32_t* par_nbr;     // level-(L-1) [slot][27] (the parents' neighbours, for interp)
 };
 
 enum ErrBits : int { kErrNoSource = 1, kErrNoChild = 2 };
@@ -69,7 +71,7 @@ struct CoalArgs {
   const void* fine0_x;        // x-face copies of fine0 and fine1
   const void* fine1_x;
   const uint32_t* pairs;      // [pair]: (direction << 16) | cell, grouped by row
-  const int32_t* chunks;      // [chunk][3]: row, first pair, end pair
+  const int32_t* chunks;      // [chunk][4]: fine_nbr row, coarse slot, first pair, end pair
   int32_t nchunks;
   const int32_t* nbr;         // level-L [slot][27]
   const int32_t* fine_nbr;    // [row][8][27]
@@ -81,6 +83,8 @@ struct CoalArgs {
   // gamma_7 sum |v| of recursive summation of 8 terms; check[2] counts pairs
   unsigned long long* check;
   int* err;                   // error bits (table lookup failures)
+  int32_t interp;             // 1: interpolated explosion of the coarse values the children trace back to
+  int32_t walls;              // 1: the forest has a non-periodic axis (no-slip walls)
 };
 
 hipError_t launch_coalesce(int storage, int n, const CoalArgs& a, hipStream_t stream);

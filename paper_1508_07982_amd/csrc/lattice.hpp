@@ -221,5 +221,51 @@ struct Geo {
   static_assert(N / W <= 16, "a cell row must fit one DPP row");
 };
 
+// ---- interpolated explosion ------------------------------------------------
+// The exploded value of a fine ghost cell in the interpolated form: each PDF
+// is reconstructed linearly inside its coarse parent P (the interpolation of
+// exploded values of Algorithm 2, section 4.1, read as a limited linear
+// reconstruction): f_a(P) + sum_d (o_d - 1/2) / 2 g_d, o the cell's octant in
+// P, g_d = minmod(f(P + e_d) - f(P), f(P) - f(P - e_d)), and g_d = 0 where a
+// face neighbour of P is no interior cell of P's level.  The 8 children of a
+// parent average to its value, and zero slopes give eq. ctof.
+template <typename C>
+__device__ __forceinline__ C minmod(C p, C q) {
+  return p * q <= C(0) ? C(0) : (fabs(p) < fabs(q) ? p : q);
+}
+
+// P = (px, py, pz): local coordinates relative to the block whose 27-entry
+// neighbour table is `tab` (entry 13: that block), at most one block away
+// (coordinates in [-N, 2N), neighbours included); buf is P's level buffer.
+// A P outside every block of that level sets an error bit and gives 0.
+template <typename S, int N>
+__device__ inline typename Form<S>::C interp_value(const S* buf, const int32_t* tab, int px, int py, int pz, int a,
+                                                  int ox, int oy, int oz, int* err) {
+  using C = typename Form<S>::C;
+  auto sd = [](int c) { return c < 0 ? -1 : (c >= N ? 1 : 0); };
+  auto at = [&](int x, int y, int z, int& ok) -> C {
+    const int b = tab[13 + sd(x) + 3 * sd(y) + 9 * sd(z)];
+    ok = b >= 0;
+    return ok ? Form<S>::ld(buf + pdf_index<N>(a, uint32_t(b), uint32_t((x & (N - 1)) + N * ((y & (N - 1)) + N * (z & (N - 1))))))
+              : C(0);
+  };
+  int ok;
+  const C f0 = at(px, py, pz, ok);
+  if (!ok) {
+    atomicOr(err, 1);
+    return C(0);
+  }
+  C v = f0;
+  const int o[3] = {ox, oy, oz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int okp, okm;
+    const C fp = at(px + (d == 0), py + (d == 1), pz + (d == 2), okp);
+    const C fm = at(px - (d == 0), py - (d == 1), pz - (d == 2), okm);
+    if (okp && okm) v += (C(o[d]) - C(0.5)) * C(0.5) * minmod<C>(fp - f0, f0 - fm);
+  }
+  return v;
+}
+
 }  // namespace dev
 }  // namespace lbm

@@ -27,7 +27,7 @@ struct LevelDev {
   int32_t* fine_nbr = nullptr;
   int32_t* fine_slot = nullptr;
   uint32_t* pairs = nullptr;    // coalesced pairs
-  int32_t* chunks = nullptr;    // coalescence work: row, first pair, end pair
+  int32_t* chunks = nullptr;    // coalescence work: fine_nbr row, slot, first pair, end pair
   int32_t nchunks = 0;
   void* coal = nullptr;         // coalesced values [fine row][19][n^3]
   void* coal_x = nullptr;       // coalesced values of x-crossing pairs [fine row][10][n^2]
@@ -82,6 +82,7 @@ struct lbm_forest {
   std::map<std::vector<int>, hipGraphExec_t> graphs;
   int* d_err = nullptr;
   bool coal_check = false;                  // FP64 accumulation check of the coalescence
+  bool interp = false;                      // interpolated explosion (lbm_set_explosion_interpolation)
   unsigned long long* d_check = nullptr;    // its figures (see CoalArgs::check)
   double* d_partials = nullptr;
   std::vector<void*> allocations;

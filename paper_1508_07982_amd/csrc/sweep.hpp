@@ -150,6 +150,54 @@ __device__ __forceinline__ const S* coarse_source(const SweepArgs& a, const Slot
   return parent_ptr<S, N, A>(a, cz, zx & (N - 1), zy & (N - 1), zz & (N - 1));
 }
 
+// The same special sources as a value, with the interpolated explosion:
+// every exploded parent value becomes the reconstruction at the fine cell
+// (interp_value in lattice.hpp, with the parents' level table).  Only the
+// sweep variant for the interpolated explosion calls it, for the cells of a
+// lane whose source is special; the direction is a run-time argument and the
+// function is not inlined, which keeps that variant small.
+template <typename S, int N>
+__device__ __noinline__ typename Form<S>::C coarse_value_rt(const S* cur, const S* prev, const S* par,
+                                                            const int32_t* nbr, const int32_t* par_nbr, int* err,
+                                                            int substep, int slot, int A, int i, int j, int k) {
+  using C = typename Form<S>::C;
+  constexpr int H = Geo<S, N>::H;
+  const int EX = ex(A), EY = ey(A), EZ = ez(A);
+  const int32_t* tab = nbr + int64_t(slot) * 27;
+  auto sd = [](int c) { return c < 0 ? -1 : (c >= N ? 1 : 0); };
+  auto parent = [&](int code, int lx, int ly, int lz, int aa) -> C {
+    const int pp = kNbrCoarse0 - code;
+    const int oc = pp & 7, pslot = pp >> 3;
+    return interp_value<S, N>(par, par_nbr + int64_t(pslot) * 27, (oc & 1 ? H : 0) + (lx >> 1),
+                              (oc & 2 ? H : 0) + (ly >> 1), (oc & 4 ? H : 0) + (lz >> 1), aa, lx & 1, ly & 1, lz & 1,
+                              err);
+  };
+  const int sx = i - EX, sy = j - EY, sz = k - EZ;
+  const int code = tab[13 + sd(sx) + 3 * sd(sy) + 9 * sd(sz)];
+  if (code == kNbrWall) return Form<S>::ld(cur + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(i + N * (j + N * k))));
+  if (code > kNbrCoarse0) {
+    atomicOr(err, kErrNoSource);
+    return C(0);
+  }
+  if (substep == 1) return parent(code, sx & (N - 1), sy & (N - 1), sz & (N - 1), A);
+  const int zx = sx - EX, zy = sy - EY, zz = sz - EZ;
+  const int cz = tab[13 + sd(zx) + 3 * sd(zy) + 9 * sd(zz)];
+  if (cz >= 0)
+    return Form<S>::ld(prev + pdf_index<N>(A, uint32_t(cz), uint32_t((zx & (N - 1)) + N * ((zy & (N - 1)) + N * (zz & (N - 1))))));
+  if (cz == kNbrWall) return parent(code, sx & (N - 1), sy & (N - 1), sz & (N - 1), opp(A));
+  if (cz > kNbrCoarse0) {
+    atomicOr(err, kErrNoSource);
+    return C(0);
+  }
+  return parent(cz, zx & (N - 1), zy & (N - 1), zz & (N - 1), A);
+}
+
+template <typename S, int N>
+__device__ __forceinline__ typename Form<S>::C coarse_value(const SweepArgs& a, int slot, int A, int i, int j, int k) {
+  return coarse_value_rt<S, N>(static_cast<const S*>(a.cur), static_cast<const S*>(a.prev),
+                               static_cast<const S*>(a.par), a.nbr, a.par_nbr, a.err, a.substep, slot, A, i, j, k);
+}
+
 // Coalescence (eq. ftoc): the value of a coalesced pair comes from the
 // coalescence launch that precedes this sweep (see CoalArgs), stored like
 // the state at the slot's fine row, or in the x-face layout for a pair that
@@ -300,14 +348,20 @@ __device__ __forceinline__ uint32_t special_cells(NbrMasks m, uint32_t fl, int i
 // Special sources of direction A for the W cells of a lane (coarse sources
 // and coalesced pairs), addressed first and loaded together: one memory
 // round trip per direction.
-template <typename S, int N, int A = 0>
+template <typename S, int N, bool INTERP, int A = 0>
 __device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, int slot, const NbrMasks& m, uint32_t fl, int i0,
                                        int j, int k, typename Form<S>::C (*h)[Geo<S, N>::W]) {
   using C = typename Form<S>::C;
   constexpr int W = Geo<S, N>::W;
   uint32_t co;
   const uint32_t spec = special_cells<N, W, A>(m, fl, i0, j, k, co);
-  if (spec) {
+  if (INTERP && spec) {
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+      if ((spec >> c) & 1u)
+        h[A][c] = (co >> c) & 1u ? C(Form<S>::ld(coalesced_source<S, N, A>(a, sc, i0 + c, j, k)))
+                                 : coarse_value<S, N>(a, slot, A, i0 + c, j, k);
+  } else if (spec) {
     C v[W];
 #pragma unroll
     for (int c = 0; c < W; ++c) {
@@ -320,7 +374,7 @@ __device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, 
     for (int c = 0; c < W; ++c)
       if ((spec >> c) & 1u) h[A][c] = v[c];
   }
-  if constexpr (A + 1 < 19) fixups<S, N, A + 1>(a, sc, slot, m, fl, i0, j, k, h);
+  if constexpr (A + 1 < 19) fixups<S, N, INTERP, A + 1>(a, sc, slot, m, fl, i0, j, k, h);
 }
 
 // Relaxation of the opposite pair (A, A + 1), e_{A+1} = -e_A: with
@@ -427,7 +481,7 @@ __device__ __forceinline__ void collide_cell(const SweepArgs& a, C (*h)[W], int 
     collide<C, W>(h, c, C(Form<S>::omega(a)));
 }
 
-template <typename S, int N, bool SIMPLE, bool TRT>
+template <typename S, int N, bool SIMPLE, bool TRT, bool INTERP>
 __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl, int cell0) {
   using C = typename Form<S>::C;
   constexpr int W = Geo<S, N>::W, N3 = Geo<S, N>::N3;
@@ -435,7 +489,7 @@ __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache&
   C h[19][W];
   uint32_t odd = 0;
   pull_all<S, N, SIMPLE>(a, sc, slot, i0, j, k, h, odd);
-  if (!SIMPLE && odd) fixups<S, N>(a, sc, slot, nbr_masks(sc), fl, i0, j, k, h);
+  if (!SIMPLE && odd) fixups<S, N, INTERP>(a, sc, slot, nbr_masks(sc), fl, i0, j, k, h);
   if (a.collide) {
 #pragma unroll
     for (int c = 0; c < W; ++c) collide_cell<S, TRT>(a, h, c);
@@ -526,12 +580,19 @@ __device__ __forceinline__ void set_half(uint32_t& w, int hi, float v) {
   w = hi ? ((w & 0xFFFFu) | (half_bits(v) << 16)) : ((w & 0xFFFF0000u) | half_bits(v));
 }
 
-template <int N, int A = 0>
+template <int N, bool INTERP, int A = 0>
 __device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& sc, int slot, const NbrMasks& m, uint32_t fl,
                                           int i0, int j, int k, uint32_t (*q)[4]) {
   uint32_t co;
   const uint32_t spec = special_cells<N, 8, A>(m, fl, i0, j, k, co);
-  if (spec) {
+  if (INTERP && spec) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if ((spec >> c) & 1u)
+        set_half(q[A][c >> 1], c & 1,
+                 (co >> c) & 1u ? Form<__half>::ld(coalesced_source<__half, N, A>(a, sc, i0 + c, j, k))
+                                : coarse_value<__half, N>(a, slot, A, i0 + c, j, k));
+  } else if (spec) {
     float v[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -544,7 +605,7 @@ __device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& s
     for (int c = 0; c < 8; ++c)
       if ((spec >> c) & 1u) set_half(q[A][c >> 1], c & 1, v[c]);
   }
-  if constexpr (A + 1 < 19) fixups_h8<N, A + 1>(a, sc, slot, m, fl, i0, j, k, q);
+  if constexpr (A + 1 < 19) fixups_h8<N, INTERP, A + 1>(a, sc, slot, m, fl, i0, j, k, q);
 }
 
 // store_face_side for the packed lane: cell 0 is the low half of register
@@ -557,7 +618,7 @@ __device__ __forceinline__ void store_face_side_h8(uint16_t* __restrict__ f, uin
   if constexpr (A + 1 < 19) store_face_side_h8<N, SIDE, A + 1>(f, row, jk, q);
 }
 
-template <int N, bool SIMPLE, bool TRT>
+template <int N, bool SIMPLE, bool TRT, bool INTERP>
 __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl,
                                                int cell0) {
   constexpr int N3 = N * N * N;
@@ -567,7 +628,7 @@ __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCac
   uint32_t odd = 0;
   issue_all_h8<N, SIMPLE>(a, sc, slot, i0, j, k, q, edge, odd);
   shift_all_h8<N>(i0, q, edge);
-  if (!SIMPLE && odd) fixups_h8<N>(a, sc, slot, nbr_masks(sc), fl, i0, j, k, q);
+  if (!SIMPLE && odd) fixups_h8<N, INTERP>(a, sc, slot, nbr_masks(sc), fl, i0, j, k, q);
   if (a.collide) {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -594,18 +655,18 @@ __device__ __forceinline__ void update_lane_h8(const SweepArgs& a, const SlotCac
   }
 }
 
-template <typename S, int N, bool SIMPLE, bool TRT>
+template <typename S, int N, bool SIMPLE, bool TRT, bool INTERP>
 __device__ __forceinline__ void update_any(const SweepArgs& a, const SlotCache& sc, int slot, uint32_t fl, int cell0) {
   if constexpr (Geo<S, N>::PACKED)
-    update_lane_h8<N, SIMPLE, TRT>(a, sc, slot, fl, cell0);
+    update_lane_h8<N, SIMPLE, TRT, INTERP>(a, sc, slot, fl, cell0);
   else
-    update_lane<S, N, SIMPLE, TRT>(a, sc, slot, fl, cell0);
+    update_lane<S, N, SIMPLE, TRT, INTERP>(a, sc, slot, fl, cell0);
 }
 
 // Work unit w: part w % SPLIT of work tile w / SPLIT (a tile split into
 // SPLIT consecutive runs of whole rows, one per workgroup of T / SPLIT
 // lanes).
-template <typename S, int N, int SPLIT, bool TRT>
+template <typename S, int N, int SPLIT, bool TRT, bool INTERP>
 __device__ __forceinline__ void sweep_item(const SweepArgs& a, int w) {
   constexpr int W = Geo<S, N>::W, CELLS = Geo<S, N>::CELLS, TPB = Geo<S, N>::TPB;
   const int item = a.work ? a.work[w / SPLIT] : a.work0 + w / SPLIT;
@@ -622,9 +683,9 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, int w) {
   if ((fl & kHasFine) && row < 0 && threadIdx.x == 0) atomicOr(a.err, kErrNoChild);
   sc.fine_row = (fl & kHasFine) && row >= 0 ? row : 0;
   if (fl & kAllSameLevel)
-    update_any<S, N, true, TRT>(a, sc, slot, fl, cell0);
+    update_any<S, N, true, TRT, INTERP>(a, sc, slot, fl, cell0);
   else
-    update_any<S, N, false, TRT>(a, sc, slot, fl, cell0);
+    update_any<S, N, false, TRT, INTERP>(a, sc, slot, fl, cell0);
 }
 
 // Workgroup splits that keep at least one full wavefront per workgroup.
@@ -646,15 +707,15 @@ __device__ __forceinline__ int xcd_unit(int b, int n) {
 // One workgroup per work unit (PERSIST = false), or a fixed grid of
 // workgroups looping over the units (PERSIST = true).  TRT: the TRT
 // collision with a body force instead of SRT.
-template <typename S, int N, bool PERSIST, int SPLIT, bool TRT = false>
+template <typename S, int N, bool PERSIST, int SPLIT, bool TRT = false, bool INTERP = false>
 __global__ void __launch_bounds__((Geo<S, N>::T / SPLIT)) sweep_kernel(SweepArgs a) {
   const int units = a.nwork * SPLIT;
   if (!PERSIST) {
     const int b = int(blockIdx.x);
-    sweep_item<S, N, SPLIT, TRT>(a, a.xcd ? xcd_unit(b, units) : b);
+    sweep_item<S, N, SPLIT, TRT, INTERP>(a, a.xcd ? xcd_unit(b, units) : b);
     return;
   }
-  for (int w = blockIdx.x; w < units; w += gridDim.x) sweep_item<S, N, SPLIT, TRT>(a, a.xcd ? xcd_unit(w, units) : w);
+  for (int w = blockIdx.x; w < units; w += gridDim.x) sweep_item<S, N, SPLIT, TRT, INTERP>(a, a.xcd ? xcd_unit(w, units) : w);
 }
 
 // Largest split <= `requested` (1, 2 or 4) valid for storage S and n.
@@ -687,7 +748,14 @@ hipError_t launch_sweep_t(int n, const SweepArgs& a, int grid, int split, hipStr
       return hipErrorInvalidValue;
     } else {
       constexpr int T = Geo<S, N>::T / SPLIT;
-      if (a.trt)
+      if (a.interp) {
+        // the interpolated explosion: one workgroup of the full tile per work tile
+        constexpr int T1 = Geo<S, N>::T;
+        if (a.trt)
+          hipLaunchKernelGGL((sweep_kernel<S, N, false, 1, true, true>), dim3(a.nwork), dim3(T1), 0, stream, a);
+        else
+          hipLaunchKernelGGL((sweep_kernel<S, N, false, 1, false, true>), dim3(a.nwork), dim3(T1), 0, stream, a);
+      } else if (a.trt)
         hipLaunchKernelGGL((sweep_kernel<S, N, false, SPLIT, true>), dim3(a.nwork * SPLIT), dim3(T), 0, stream, a);
       else if (grid < a.nwork * SPLIT)
         hipLaunchKernelGGL((sweep_kernel<S, N, true, SPLIT>), dim3(grid), dim3(T), 0, stream, a);

@@ -74,6 +74,7 @@ _SIGNATURES = {
     "lbm_mass": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
     "lbm_set_schedule": [ctypes.c_void_p, ctypes.c_int],
     "lbm_set_coalescence_check": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_set_explosion_interpolation": [ctypes.c_void_p, ctypes.c_int],
     "lbm_coalescence_check": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_launch": [ctypes.c_void_p, ctypes.c_int],
     "lbm_synchronize": [ctypes.c_void_p],
@@ -279,6 +280,10 @@ class Forest:
 
     def set_schedule(self, schedule: str):
         _check(self._lib.lbm_set_schedule(self._h, SCHEDULE[schedule]))
+
+    def set_explosion_interpolation(self, on: bool = True):
+        """Limited linear reconstruction of exploded values (see the header)."""
+        _check(self._lib.lbm_set_explosion_interpolation(self._h, int(bool(on))))
 
     def set_coalescence_check(self, on: bool = True):
         _check(self._lib.lbm_set_coalescence_check(self._h, int(bool(on))))
