@@ -177,6 +177,45 @@ def batching_form(torch, lbm, W, stream):
     return out
 
 
+def inplace_form(torch, lbm, W, stream, storage):
+    """Two-buffer against in-place (AA pattern) streaming on the uniform
+    periodic grid of 16^3 roots of 32^3 cells (512^3 cells, one level):
+    MLUPS, mean time and algorithmic GB/s of each launch kind, and the
+    device memory the forest holds (free memory before creating it and
+    after switching in-place streaming on)."""
+    wu = W.config_uniform(32, 16)
+    s = BYTES[storage]
+    out = {"workload": wu.name, "description": wu.description, "storage": storage}
+    rho = u = None
+    for label in ("two_buffer", "in_place"):
+        torch.cuda.synchronize()
+        free0, _ = lbm.device_memory(0)
+        g = lbm.Forest(wu.R, wu.n, 0, storage=storage, stream=stream.cuda_stream)
+        if rho is None:
+            rho, u = W.initial_field(wu, g.leaves())
+        g.set_level_omega(wu.omega0)
+        g.init_pdfs(rho, u)
+        if label == "in_place":
+            g.set_inplace(True)
+        g.synchronize()
+        free1, _ = lbm.device_memory(0)
+        N = g.num_cells()
+        g.step_coarse(2)
+        ms = timed_steps(torch, g, stream, 10)
+        sweeps = g.time_sweeps(2)
+        launches = {}
+        for (L, sub), (m, c) in sorted(sweeps.items()):
+            key = ("odd" if sub == 1 else "even") if label == "in_place" else "sweep"
+            launches[key] = {"ms": round(m, 4), "launches": c, "GBps": round(38 * s * N / (m * 1e-3) / 1e9, 1)}
+        out["cells"] = N
+        out[label] = {"MLUPS": round(N / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+                      "device_bytes": int(free0 - free1), "pdf_buffer_bytes": N * 19 * s, "launches": launches}
+        g.close()
+        del g
+    out["device_bytes_ratio"] = round(out["in_place"]["device_bytes"] / out["two_buffer"]["device_bytes"], 4)
+    return out
+
+
 def ceilings_now(torch, lbm):
     """The copy probe and the sweep-shape probe at the finest level's size
     (FP64 elements, 2368 blocks of 32^3 cells), measured in this run."""
@@ -253,7 +292,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the FP32/FP16, TRT, batching and per-block comparison runs")
+                    help="skip the FP32/FP16, TRT, interpolation, batching, per-block and in-place comparison runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
     args = ap.parse_args()
@@ -311,6 +350,10 @@ def main():
                                          "ms_per_step": round(msp, 3)}
         gp.close()
         del gp
+        for storage in ("f64", "f32", "f16"):
+            forms[f"{storage}_inplace_uniform"] = inplace_form(torch, lbm, W, stream, storage)
+            print(f"{storage} in place: {forms[storage + '_inplace_uniform']['in_place']['MLUPS']} MLUPS",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
 
     out = {

@@ -220,6 +220,36 @@ int lbm_mass(lbm_forest *f, double *mass, double momentum[3]);
  * homogeneously.  Invalidates captured graphs. */
 int lbm_set_explosion_interpolation(lbm_forest *f, int on);
 
+/* In-place streaming (on != 0; off by default).  Section 4.1 stores two
+ * grids, source and destination, and names the AA pattern as the in-place
+ * alternative that refinement does not readily admit.  The library builds
+ * it for forests whose leaves all lie on level 0 (no level interfaces):
+ * level 0 keeps one PDF buffer and its x-face copy instead of two, which
+ * halves the device memory of the PDFs; the bytes moved per cell update
+ * stay 38 s (19 values read and 19 written).  Coarse steps alternate an
+ * odd launch (pull from the neighbours, collide, push to them) and an even
+ * one (collide in place); the buffer holds the post-collision state in a
+ * layout that alternates with them and is brought back to the natural
+ * layout, in place, before lbm_get_moments, lbm_get_moments_static,
+ * lbm_mass, lbm_get_pdfs or the indicator calls read it.  Results equal
+ * those of two-buffer streaming bitwise, SRT and TRT with a body force,
+ * periodic axes and no-slip walls alike.  on = 1 frees the second buffer
+ * (after synchronizing the stream); on = 0 allocates it again.  While on,
+ * lbm_autotune and lbm_regrid return LBM_E_STATE, and lbm_regrid also does
+ * until a coarse step with two-buffer streaming has been taken (it needs
+ * the state at the start of the last coarse step).  Invalidates captured
+ * graphs.  Errors: LBM_E_INVALID (on not 0 or 1; on = 1 on a forest with
+ * more than one level), LBM_E_OOM (on = 0), LBM_E_HIP. */
+int lbm_set_inplace(lbm_forest *f, int on);
+
+/* Whether in-place streaming is on (*on = 1) or off (0). */
+int lbm_get_inplace(const lbm_forest *f, int *on);
+
+/* Free and total device memory of `device` in bytes (hipMemGetInfo): for
+ * sizing forests, and to see the memory lbm_set_inplace releases.  Errors:
+ * LBM_E_INVALID, LBM_E_HIP. */
+int lbm_device_memory(int device, int64_t *free_bytes, int64_t *total_bytes);
+
 /* FP64 accumulation check of the coalescence (eq. ftoc, section 4.4).  With
  * FP32 or FP16 storage the 8-child sums are formed in FP32; with the check
  * on (on != 0; off by default) every coalescence launch also sums the same

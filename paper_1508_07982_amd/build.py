@@ -18,7 +18,7 @@ LIB = os.path.join(LIBDIR, "liblbm_refined.so")
 BUILD = os.path.join(ROOT, "_build")
 
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["forest.cpp", "kernels.hip", "sweep_f64.hip", "sweep_f32.hip", "sweep_f16.hip", "api.hip", "indicator.hip", "probe.hip"]
+SOURCES = ["forest.cpp", "kernels.hip", "sweep_f64.hip", "sweep_f32.hip", "sweep_f16.hip", "api.hip", "indicator.hip", "probe.hip", "inplace.hip"]
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 ops are not emitted: some of their forms have given wrong

@@ -30,6 +30,7 @@
 
 #include "../../include/lbm_refined.h"
 #include "forest.hpp"
+#include "inplace.hpp"
 #include "kernels.hpp"
 #include "state.hpp"
 
@@ -355,6 +356,72 @@ int check_err_flag(lbm_forest* f) {
 
 const void* current_buffer(const lbm_forest* f, int L) { return f->lv[L].buf[f->rot[L]]; }
 
+// ---- in-place streaming (lbm_set_inplace; layouts in inplace.hpp) ----------
+
+InplaceArgs inplace_args(const lbm_forest* f) {
+  const LevelDev& v = f->lv[0];
+  InplaceArgs a;
+  a.buf = v.buf[0];
+  a.face = v.xface[0];
+  a.nbr = v.nbr;
+  a.nblocks = v.nblocks;
+  a.xcd = v.order;
+  a.trt = f->trt ? 1 : 0;
+  a.omega = float(v.omega);
+  a.omega64 = v.omega;
+  a.lambda_o = float(v.lambda_o);
+  a.lambda_o64 = v.lambda_o;
+  for (int d = 0; d < 3; ++d) {
+    a.accel[d] = float(v.accel[d]);
+    a.accel64[d] = v.accel[d];
+  }
+  return a;
+}
+
+// From the natural layout to the swapped one, with the x-face copy that the
+// odd launch reads.
+int inplace_begin(lbm_forest* f) {
+  if (f->layout != kLayoutNatural) return LBM_OK;
+  const LevelDev& v = f->lv[0];
+  HIP_TRY(launch_face_copy(f->storage, f->n, v.buf[0], v.xface[0], v.nblocks, f->stream));
+  HIP_TRY(launch_inplace_swap(f->storage, f->n, v.buf[0], v.nblocks, f->stream));
+  f->layout = kLayoutSwapped;
+  return LBM_OK;
+}
+
+// One in-place coarse step: the odd launch from the swapped layout, the
+// even one from the pushed layout.
+int inplace_step(lbm_forest* f) {
+  const bool odd = f->layout == kLayoutSwapped;
+  if (f->schedule == LBM_SCHED_GRAPH) {
+    const std::vector<int> key = {-1, odd ? 1 : 0};  // rotation keys are non-negative
+    auto it = f->graphs.find(key);
+    if (it == f->graphs.end()) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t ge = nullptr;
+      HIP_TRY(hipStreamBeginCapture(f->stream, hipStreamCaptureModeThreadLocal));
+      const hipError_t le = launch_inplace(f->storage, f->n, inplace_args(f), odd, f->stream);
+      const hipError_t ce = hipStreamEndCapture(f->stream, &g);
+      if (le != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(LBM_E_HIP, "graph capture of the in-place launch: %s",
+                    hipGetErrorString(le != hipSuccess ? le : ce));
+      }
+      const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) return fail(LBM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+      it = f->graphs.emplace(key, ge).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, f->stream));
+  } else {
+    HIP_TRY(launch_inplace(f->storage, f->n, inplace_args(f), odd, f->stream));
+  }
+  f->layout = odd ? kLayoutPushed : kLayoutSwapped;
+  f->steps_since_state++;
+  f->post_lost = true;
+  return LBM_OK;
+}
+
 // Staging memory of lbm_get_moments_static: a file-scope device array, so
 // that the call allocates nothing.  Each device holds its own copy, at an
 // address that hipGetSymbolAddress gives once per device (the array's name
@@ -382,6 +449,15 @@ int moments_stage(int device, double** out) {
 void* current_buffer_mut(lbm_forest* f, int L) { return f->lv[L].buf[f->rot[L]]; }
 
 }  // namespace
+
+int lbm::prepare_state_read(lbm_forest* f) {
+  if (!f->inplace || f->layout == kLayoutNatural) return LBM_OK;
+  const LevelDev& v = f->lv[0];
+  if (f->layout == kLayoutPushed) HIP_TRY(launch_inplace_pair_swap(f->storage, f->n, v.buf[0], v.nbr, v.nblocks, f->stream));
+  HIP_TRY(launch_inplace_swap(f->storage, f->n, v.buf[0], v.nblocks, f->stream));
+  f->layout = kLayoutNatural;
+  return LBM_OK;
+}
 
 extern "C" {
 
@@ -644,6 +720,8 @@ int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
     int64_t off = 0;
     std::fill(f->rot.begin(), f->rot.end(), 0);
     f->steps_since_state = 0;
+    f->layout = kLayoutNatural;
+    f->post_lost = false;
     for (size_t L = 0; L < f->lv.size(); ++L) {
       const LevelDev& v = f->lv[L];
       HIP_TRY(launch_init(f->storage, f->n, v.buf[0], d_rho + off, d_u + 3 * off, v.ncells, level_accel(f, int(L)),
@@ -660,6 +738,71 @@ int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
   (void)hipFree(d_rho);
   (void)hipFree(d_u);
   return rc;
+}
+
+int lbm_set_inplace(lbm_forest* f, int on) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  if (on != 0 && on != 1) return fail(LBM_E_INVALID, "on must be 0 or 1");
+  if ((on != 0) == f->inplace) return LBM_OK;
+  HIP_TRY(hipSetDevice(f->device));
+  LevelDev& v = f->lv[0];
+  if (on) {
+    if (f->lv.size() != 1)
+      return fail(LBM_E_INVALID,
+                  "in-place streaming is built for forests whose leaves all lie on level 0 (this forest has %zu "
+                  "levels): level interfaces read states that an in-place update overwrites",
+                  f->lv.size());
+    // nothing queued may still use the buffer that is released
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    if (f->rot[0] != 0) {
+      std::swap(v.buf[0], v.buf[1]);
+      std::swap(v.xface[0], v.xface[1]);
+      f->rot[0] = 0;
+    }
+    f->rot_prev = f->rot;
+    for (void* p : {v.buf[1], v.xface[1]}) {
+      auto it = std::find(v.allocs.begin(), v.allocs.end(), p);
+      if (it != v.allocs.end()) v.allocs.erase(it);
+      if (p) HIP_TRY(hipFree(p));
+    }
+    v.buf[1] = nullptr;
+    v.xface[1] = nullptr;
+    v.nbuf = 1;
+    f->inplace = true;
+    f->layout = kLayoutNatural;
+  } else {
+    int rc = prepare_state_read(f);
+    if (rc) return rc;
+    const size_t sb = storage_bytes(f->storage);
+    uint8_t* p = nullptr;
+    if ((rc = dev_alloc(v.allocs, &p, size_t(v.plane) * 19 * sb))) return rc;
+    v.buf[1] = p;
+    if ((rc = dev_alloc(v.allocs, &p, size_t(v.nblocks) * 10 * f->n * f->n * sb))) return rc;
+    v.xface[1] = p;
+    v.nbuf = 2;
+    HIP_TRY(launch_face_copy(f->storage, f->n, v.buf[0], v.xface[0], v.nblocks, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    f->inplace = false;
+    f->rot_prev = f->rot;
+  }
+  invalidate_graphs(f);
+  return LBM_OK;
+}
+
+int lbm_device_memory(int device, int64_t* free_bytes, int64_t* total_bytes) {
+  if (!free_bytes || !total_bytes) return fail(LBM_E_INVALID, "null pointer");
+  HIP_TRY(hipSetDevice(device));
+  size_t fr = 0, tot = 0;
+  HIP_TRY(hipMemGetInfo(&fr, &tot));
+  *free_bytes = int64_t(fr);
+  *total_bytes = int64_t(tot);
+  return LBM_OK;
+}
+
+int lbm_get_inplace(const lbm_forest* f, int* on) {
+  if (!f || !on) return fail(LBM_E_INVALID, "null pointer");
+  *on = f->inplace ? 1 : 0;
+  return LBM_OK;
 }
 
 int lbm_set_explosion_interpolation(lbm_forest* f, int on) {
@@ -735,6 +878,7 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
   if (!f || !result) return fail(LBM_E_INVALID, "null pointer");
   if (n_steps < 1) return fail(LBM_E_INVALID, "n_steps < 1");
   if (!f->omega_set) return fail(LBM_E_STATE, "lbm_set_level_omega must be called first");
+  if (f->inplace) return fail(LBM_E_STATE, "the autotuner times the two-buffer sweep; switch in-place streaming off first");
   HIP_TRY(hipSetDevice(f->device));
   const int nl = int(f->lv.size());
   const size_t sb = storage_bytes(f->storage);
@@ -827,12 +971,18 @@ int lbm_step_coarse(lbm_forest* f, int n_steps) {
   if (n_steps < 0) return fail(LBM_E_INVALID, "n_steps < 0");
   if (!f->omega_set) return fail(LBM_E_STATE, "lbm_set_level_omega must be called first");
   HIP_TRY(hipSetDevice(f->device));
+  if (f->inplace) {
+    int rc = n_steps > 0 ? inplace_begin(f) : LBM_OK;
+    for (int s = 0; s < n_steps && !rc; ++s) rc = inplace_step(f);
+    return rc;
+  }
   for (int s = 0; s < n_steps; ++s) {
     std::vector<int> r = f->rot;
     std::vector<Op> ops;
     emit(f, 0, 1, r, nullptr, ops);
     f->rot_prev = f->rot;
     f->steps_since_state++;
+    f->post_lost = false;
     if (f->schedule == LBM_SCHED_GRAPH) {
       auto it = f->graphs.find(f->rot);
       if (it == f->graphs.end()) {
@@ -871,12 +1021,32 @@ int lbm_time_launches(lbm_forest* f, int n_steps, double* ms, int64_t* launches,
     for (auto& e : ends) (void)hipEventDestroy(e);
   };
   auto body = [&]() -> int {
-    for (int s = 0; s < n_steps; ++s) {
+    if (f->inplace) {
+      // in-place streaming: the odd launch counts as substep 1, the even one as substep 2
+      int rc = inplace_begin(f);
+      if (rc) return rc;
+      for (int s = 0; s < n_steps; ++s) {
+        const bool odd = f->layout == kLayoutSwapped;
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        marks.emplace_back(odd ? 0 : 1, e0);
+        HIP_TRY(hipEventCreate(&e1));
+        ends.push_back(e1);
+        HIP_TRY(hipEventRecord(e0, f->stream));
+        HIP_TRY(launch_inplace(f->storage, f->n, inplace_args(f), odd, f->stream));
+        HIP_TRY(hipEventRecord(e1, f->stream));
+        f->layout = odd ? kLayoutPushed : kLayoutSwapped;
+        f->steps_since_state++;
+        f->post_lost = true;
+      }
+    }
+    for (int s = 0; s < n_steps && !f->inplace; ++s) {
       std::vector<int> r = f->rot;
       std::vector<Op> ops;
       emit(f, 0, 1, r, nullptr, ops);
       f->rot_prev = f->rot;
       f->steps_since_state++;
+      f->post_lost = false;
       for (const Op& op : ops) {
         const bool coal = op.kind == Op::kCoalesce;
         if (!coal && op.args.nwork <= 0) continue;
@@ -922,6 +1092,10 @@ int lbm_time_launches(lbm_forest* f, int n_steps, double* ms, int64_t* launches,
 
 int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
   if (!f || (!flags && count)) return fail(LBM_E_INVALID, "null pointer");
+  if (f->inplace || f->post_lost)
+    return fail(LBM_E_STATE,
+                "regrid needs the state at the start of the last coarse step, which in-place streaming does not "
+                "keep: switch it off and take a coarse step first");
   if (f->trt) return fail(LBM_E_STATE, "regrid supports the SRT collision without a body force");
   HIP_TRY(hipSetDevice(f->device));
   int rc = check_err_flag(f);
@@ -1107,6 +1281,7 @@ int lbm_get_moments(lbm_forest* f, double* rho, double* u) {
   HIP_TRY(hipSetDevice(f->device));
   int rc = check_err_flag(f);
   if (rc) return rc;
+  if ((rc = prepare_state_read(f))) return rc;
   int64_t off = 0;
   for (size_t L = 0; L < f->lv.size(); ++L) {
     const LevelDev& v = f->lv[L];
@@ -1137,6 +1312,7 @@ int lbm_get_moments_static(lbm_forest* f, double* rho, double* u) {
   int rc = moments_stage(f->device, &stage);
   if (rc) return rc;
   if ((rc = check_err_flag(f))) return rc;
+  if ((rc = prepare_state_read(f))) return rc;
   int64_t off = 0;
   for (size_t L = 0; L < f->lv.size(); ++L) {
     const LevelDev& v = f->lv[L];
@@ -1160,6 +1336,7 @@ int lbm_get_moments_static(lbm_forest* f, double* rho, double* u) {
 int lbm_get_pdfs(lbm_forest* f, double* h) {
   if (!f || !h) return fail(LBM_E_INVALID, "null pointer");
   HIP_TRY(hipSetDevice(f->device));
+  if (int rc = prepare_state_read(f)) return rc;
   int64_t off = 0;
   for (size_t L = 0; L < f->lv.size(); ++L) {
     const LevelDev& v = f->lv[L];
@@ -1194,6 +1371,8 @@ int lbm_set_pdfs(lbm_forest* f, const double* h) {
       HIP_TRY(launch_set_pdfs(f->storage, f->n, current_buffer_mut(f, int(L)), d, v.ncells, f->stream));
       f->steps_since_state = 0;
       f->state_set = true;
+      f->layout = kLayoutNatural;
+      f->post_lost = false;
       HIP_TRY(launch_face_copy(f->storage, f->n, current_buffer(f, int(L)), v.xface[f->rot[L]], v.nblocks,
                                f->stream));
       HIP_TRY(hipStreamSynchronize(f->stream));
@@ -1212,6 +1391,7 @@ int lbm_mass(lbm_forest* f, double* mass, double momentum[3]) {
   HIP_TRY(hipSetDevice(f->device));
   int rc = check_err_flag(f);
   if (rc) return rc;
+  if ((rc = prepare_state_read(f))) return rc;
   const size_t nl = f->lv.size();
   for (size_t L = 0; L < nl; ++L) {
     if (f->lv[L].ncells == 0) continue;

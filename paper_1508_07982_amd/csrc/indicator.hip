@@ -567,6 +567,7 @@ int lbm_plain_targets(const double* crit, int64_t n, double theta_omega, double 
 int lbm_block_indicators(lbm_forest* f, double* features, double* crit) {
   if (!f || !features || !crit) return set_error(LBM_E_INVALID, "null pointer");
   TRY(hipSetDevice(f->device));
+  if (int rc0 = prepare_state_read(f)) return rc0;
   int64_t nb = 0, maxcells = 0;
   for (const auto& v : f->lv) {
     nb += v.nblocks;
@@ -598,6 +599,7 @@ int lbm_block_indicators(lbm_forest* f, double* features, double* crit) {
 int lbm_block_features(lbm_forest* f, double* features) {
   if (!f || !features) return set_error(LBM_E_INVALID, "null pointer");
   TRY(hipSetDevice(f->device));
+  if (int rc0 = prepare_state_read(f)) return rc0;
   int64_t nb = 0;
   for (const auto& v : f->lv) nb += v.nblocks;
   Scratch sc;
@@ -811,6 +813,7 @@ int lbm_refinement_flags(lbm_forest* f, lbm_mlp* m, double theta_omega, double t
   if (!(theta_omega > 0) || !(theta_neq > 0) || delta < 0) return set_error(LBM_E_INVALID, "bad thresholds");
   if (m && m->device != f->device) return set_error(LBM_E_INVALID, "MLP and forest on different devices");
   TRY(hipSetDevice(f->device));
+  if (int rc0 = prepare_state_read(f)) return rc0;
   const int nlev = int(f->lv.size());
   int64_t nb = 0, maxcells = 0;
   std::vector<int64_t> first(nlev, 0);

@@ -1,0 +1,641 @@
+// In-place streaming (AA pattern) kernels: the odd and even launches and the
+// layout conversions (layouts and ownership in inplace.hpp).
+//
+// Work decomposition as in the two-buffer sweep: one workgroup per tile of
+// one block, each lane W x-consecutive cells of one row (W = the storage
+// form's 16-byte vector; packed FP16 pairs, 8 cells, for FP16 blocks of 8 or
+// more cells per row), x shifts by one cell as DPP
+// moves between the lanes of a row.  The even launch touches only the
+// lane's own cells.  The odd launch reads and writes the lane's
+// neighbours: rows shifted in y and z are whole vectors in the neighbour
+// block (found in the scalar neighbour table), rows shifted in x come from
+// the adjacent lane, and at a block's x face one element per row end
+// crosses to the x neighbour: read from the x-face copy that the even
+// launch wrote, written as a single element.  The first lane of a row
+// (e_x = +1) or the last (e_x = -1) leaves the crossing position to the x
+// neighbour's workgroup and stores the rest of its vector element-wise.
+#include "inplace.hpp"
+#include "sweep.hpp"
+
+namespace lbm {
+namespace dev {
+
+// Cells per lane as in the two-buffer sweep: FP16 blocks of 8 or more
+// cells per row keep 8 cells per lane as packed half pairs (16-byte
+// accesses, the packed launches below); otherwise the storage form's vector.
+template <typename S, int N>
+struct IGeo {
+  static constexpr bool PACKED = sizeof(S) == 2 && N >= 8;
+  static constexpr int W = PACKED ? 8 : Vec<S>::W;
+  static constexpr int N3 = N * N * N;
+  static constexpr int CELLS = N3 < 256 * W ? N3 : 256 * W;  // cells per workgroup
+  static constexpr int T = CELLS / W;                          // lanes per workgroup
+  static constexpr int TPB = N3 / CELLS;                       // tiles per block
+  static_assert(N % W == 0 && N / W <= 16, "a cell row must fit one DPP row");
+};
+
+template <typename S>
+struct IParm;
+template <>
+struct IParm<double> {
+  static __device__ __forceinline__ double om(const InplaceArgs& a) { return a.omega64; }
+  static __device__ __forceinline__ double lo(const InplaceArgs& a) { return a.lambda_o64; }
+  static __device__ __forceinline__ double ac(const InplaceArgs& a, int d) { return a.accel64[d]; }
+};
+template <typename S>
+struct IParm {
+  static __device__ __forceinline__ float om(const InplaceArgs& a) { return a.omega; }
+  static __device__ __forceinline__ float lo(const InplaceArgs& a) { return a.lambda_o; }
+  static __device__ __forceinline__ float ac(const InplaceArgs& a, int d) { return a.accel[d]; }
+};
+
+template <typename S, bool TRT, typename C, int W>
+__device__ __forceinline__ void icollide(const InplaceArgs& a, C (*h)[W], int c) {
+  using P = IParm<S>;
+  if constexpr (TRT)
+    collide_trt<C, W>(h, c, C(P::om(a)), C(P::lo(a)), C(P::ac(a, 0)), C(P::ac(a, 1)), C(P::ac(a, 2)));
+  else
+    collide<C, W>(h, c, C(P::om(a)));
+}
+
+// The tile of workgroup b: block slot (wave-uniform) and the lane's first cell.
+template <typename S, int N>
+__device__ __forceinline__ void tile_of(const InplaceArgs& a, int& slot, int& cell0) {
+  constexpr int TPB = IGeo<S, N>::TPB, CELLS = IGeo<S, N>::CELLS, W = IGeo<S, N>::W;
+  const int units = a.nblocks * TPB;
+  const int b = int(blockIdx.x);
+  const int unit = a.xcd ? xcd_unit(b, units) : b;
+  slot = __builtin_amdgcn_readfirstlane(unit / TPB);
+  cell0 = (unit - slot * TPB) * CELLS + int(threadIdx.x) * W;
+}
+
+__device__ __forceinline__ void load_table(const InplaceArgs& a, int slot, SlotCache& sc) {
+  const int32_t* nb = a.nbr + int64_t(slot) * 27;
+#pragma unroll
+  for (int q = 0; q < 27; ++q) sc.nbr[q] = __builtin_amdgcn_readfirstlane(nb[q]);
+  sc.fine_row = 0;
+}
+
+// ---- odd launch: swapped -> pushed ------------------------------------------
+
+// Issue the loads of direction A: f*_A(x - e_A) sits at (x - e_A, opp(A)).
+// Bit A of `wall` marks a source beyond a wall for some cell of the lane.
+template <typename S, int N, int A>
+__device__ __forceinline__ void odd_issue(const InplaceArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
+                                          typename Form<S>::C (*h)[IGeo<S, N>::W], typename Form<S>::C* edge,
+                                          uint32_t& wall) {
+  constexpr int W = IGeo<S, N>::W;
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  const int sy = j - EY, sz = k - EZ;
+  const bool by = outside<N>(sy), bz = outside<N>(sz);
+  const uint32_t row = uint32_t(N * ((sy & (N - 1)) + N * (sz & (N - 1))));
+  const int nbm = pick<0, -EY, -EZ>(sc, false, by, bz);
+  wall |= uint32_t(nbm < 0) << A;
+  const S* __restrict__ buf = static_cast<const S*>(a.buf);
+  Vec<S>::load(buf + pdf_index<N>(opp(A), uint32_t(nbm >= 0 ? nbm : slot), row + uint32_t(i0)), h[A]);
+  if constexpr (EX != 0) {
+    const bool at_end = EX == 1 ? i0 == 0 : i0 == N - W;
+    const int nbx = pick<-EX, -EY, -EZ>(sc, true, by, bz);
+    wall |= uint32_t(at_end && nbx < 0) << A;
+    // f*_A of the x neighbour's end cell: the value leaving it through its x face
+    const int eb = nbx >= 0 ? nbx : slot;
+    edge[xdir_index(A)] = Form<S>::ld(static_cast<const S*>(a.face) + xface_index<N, A>(uint32_t(eb), row / N));
+  }
+}
+
+template <typename S, int N, int A = 0>
+__device__ __forceinline__ void odd_issue_all(const InplaceArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
+                                              typename Form<S>::C (*h)[IGeo<S, N>::W], typename Form<S>::C* edge,
+                                              uint32_t& wall) {
+  odd_issue<S, N, A>(a, sc, slot, i0, j, k, h, edge, wall);
+  if constexpr (A + 1 < 19) odd_issue_all<S, N, A + 1>(a, sc, slot, i0, j, k, h, edge, wall);
+}
+
+template <typename S, int N, int A = 0>
+__device__ __forceinline__ void odd_shift_all(int i0, typename Form<S>::C (*h)[IGeo<S, N>::W],
+                                              const typename Form<S>::C* edge) {
+  using C = typename Form<S>::C;
+  constexpr int W = IGeo<S, N>::W;
+  constexpr int EX = ex(A);
+  if constexpr (EX == 1) {  // source x - 1
+    const C prev = dpp_move<kDppRowShr1>(h[A][W - 1]);
+#pragma unroll
+    for (int c = W - 1; c > 0; --c) h[A][c] = h[A][c - 1];
+    h[A][0] = i0 == 0 ? edge[xdir_index(A)] : prev;
+  } else if constexpr (EX == -1) {  // source x + 1
+    const C next = dpp_move<kDppRowShl1>(h[A][0]);
+#pragma unroll
+    for (int c = 0; c < W - 1; ++c) h[A][c] = h[A][c + 1];
+    h[A][W - 1] = i0 == N - W ? edge[xdir_index(A)] : next;
+  }
+  if constexpr (A + 1 < 19) odd_shift_all<S, N, A + 1>(i0, h, edge);
+}
+
+// Sources beyond a wall: the cell's own post-collision value of the
+// opposite direction, f*_opp(A)(x), which the swapped layout keeps at
+// (x, A) (halfway bounce-back).
+template <typename S, int N, int A = 1>
+__device__ __forceinline__ void odd_walls(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0, int j,
+                                          int k, uint32_t wall, typename Form<S>::C (*h)[IGeo<S, N>::W]) {
+  constexpr int W = IGeo<S, N>::W;
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  if ((wall >> A) & 1u) {
+    const int sy = j - EY, sz = k - EZ;
+    const bool by = outside<N>(sy), bz = outside<N>(sz);
+    uint32_t cells = 0;
+    if (pick<0, -EY, -EZ>(sc, false, by, bz) < 0) {
+      cells = (1u << W) - 1u;
+    } else if constexpr (EX != 0) {
+      const bool at_end = EX == 1 ? i0 == 0 : i0 == N - W;
+      if (at_end && pick<-EX, -EY, -EZ>(sc, true, by, bz) < 0) cells = EX == 1 ? 1u : 1u << (W - 1);
+    }
+    const S* __restrict__ own = static_cast<const S*>(a.buf) + pdf_index<N>(A, uint32_t(slot), uint32_t(cell0));
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+      if ((cells >> c) & 1u) h[A][c] = Form<S>::ld(own + c);
+  }
+  if constexpr (A + 1 < 19) odd_walls<S, N, A + 1>(a, sc, slot, cell0, i0, j, k, wall, h);
+}
+
+// Store direction A: f*_A(x) to (x + e_A, A), or to (x, opp(A)) where x + e_A
+// lies beyond a wall.
+template <typename S, int N, int A>
+__device__ __forceinline__ void odd_store(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0, int j,
+                                          int k, typename Form<S>::C (*h)[IGeo<S, N>::W]) {
+  using C = typename Form<S>::C;
+  constexpr int W = IGeo<S, N>::W;
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  S* __restrict__ buf = static_cast<S*>(a.buf);
+  const int dy = j + EY, dz = k + EZ;
+  const bool by = outside<N>(dy), bz = outside<N>(dz);
+  const uint32_t row = uint32_t(N * ((dy & (N - 1)) + N * (dz & (N - 1))));
+  const int nbd = pick<0, EY, EZ>(sc, false, by, bz);
+  S* __restrict__ own = buf + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(cell0));
+  // x shift of the row by one cell (DPP, every lane takes part)
+  C v[W];
+  if constexpr (EX == 1) {
+    const C prev = dpp_move<kDppRowShr1>(h[A][W - 1]);
+    v[0] = prev;
+#pragma unroll
+    for (int c = 1; c < W; ++c) v[c] = h[A][c - 1];
+  } else if constexpr (EX == -1) {
+    const C next = dpp_move<kDppRowShl1>(h[A][0]);
+#pragma unroll
+    for (int c = 0; c < W - 1; ++c) v[c] = h[A][c + 1];
+    v[W - 1] = next;
+  }
+  if (nbd < 0) {  // the whole destination row lies beyond a wall: every cell reflects
+    Vec<S>::store(own, h[A]);
+    return;
+  }
+  S* __restrict__ dst = buf + pdf_index<N>(A, uint32_t(nbd), row + uint32_t(i0));
+  if constexpr (EX == 0) {
+    Vec<S>::store(dst, h[A]);
+  } else {
+    constexpr int KEEP = EX == 1 ? 0 : W - 1;  // position owned by the x neighbour's end cell
+    const bool crossing_lane = EX == 1 ? i0 == 0 : i0 == N - W;
+    if (crossing_lane) {
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        if (c != KEEP) Form<S>::st(dst + c, v[c]);
+    } else {
+      Vec<S>::store(dst, v);
+    }
+    // the end cell whose destination lies in the x neighbour (or beyond a wall)
+    const bool leaving_lane = EX == 1 ? i0 == N - W : i0 == 0;
+    if (leaving_lane) {
+      constexpr int END = EX == 1 ? W - 1 : 0;
+      const int nbx = pick<EX, EY, EZ>(sc, true, by, bz);
+      if (nbx >= 0)
+        Form<S>::st(buf + pdf_index<N>(A, uint32_t(nbx), row + uint32_t(EX == 1 ? 0 : N - 1)), h[A][END]);
+      else
+        Form<S>::st(own + END, h[A][END]);
+    }
+  }
+}
+
+template <typename S, int N, int A = 0>
+__device__ __forceinline__ void odd_store_all(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0,
+                                              int j, int k, typename Form<S>::C (*h)[IGeo<S, N>::W]) {
+  odd_store<S, N, A>(a, sc, slot, cell0, i0, j, k, h);
+  if constexpr (A + 1 < 19) odd_store_all<S, N, A + 1>(a, sc, slot, cell0, i0, j, k, h);
+}
+
+template <typename S, int N, bool TRT>
+__global__ void __launch_bounds__((IGeo<S, N>::T)) inplace_odd_kernel(InplaceArgs a) {
+  using C = typename Form<S>::C;
+  constexpr int W = IGeo<S, N>::W;
+  int slot, cell0;
+  tile_of<S, N>(a, slot, cell0);
+  SlotCache sc;
+  load_table(a, slot, sc);
+  const int i0 = cell0 & (N - 1), j = (cell0 / N) & (N - 1), k = cell0 / (N * N);
+  C h[19][W];
+  C edge[kXDirs];
+  uint32_t wall = 0;
+  odd_issue_all<S, N>(a, sc, slot, i0, j, k, h, edge, wall);
+  odd_shift_all<S, N>(i0, h, edge);
+  if (wall) odd_walls<S, N>(a, sc, slot, cell0, i0, j, k, wall, h);
+#pragma unroll
+  for (int c = 0; c < W; ++c) icollide<S, TRT>(a, h, c);
+  odd_store_all<S, N>(a, sc, slot, cell0, i0, j, k, h);
+}
+
+// ---- even launch: pushed -> swapped -------------------------------------------
+
+template <typename S, int N, bool TRT>
+__global__ void __launch_bounds__((IGeo<S, N>::T)) inplace_even_kernel(InplaceArgs a) {
+  using C = typename Form<S>::C;
+  constexpr int W = IGeo<S, N>::W, N3 = N * N * N;
+  int slot, cell0;
+  tile_of<S, N>(a, slot, cell0);
+  const int i0 = cell0 & (N - 1), j = (cell0 / N) & (N - 1), k = cell0 / (N * N);
+  S* __restrict__ p = static_cast<S*>(a.buf) + pdf_index<N>(0, uint32_t(slot), uint32_t(cell0));
+  C h[19][W];
+#pragma unroll
+  for (int d = 0; d < 19; ++d) Vec<S>::load(p + d * N3, h[d]);
+#pragma unroll
+  for (int c = 0; c < W; ++c) icollide<S, TRT>(a, h, c);
+#pragma unroll
+  for (int d = 0; d < 19; ++d) Vec<S>::store(p + opp(d) * N3, h[d]);
+  // x-face copy for the next odd launch: the values leaving the block
+  // through its x faces, by direction
+  S* __restrict__ f = static_cast<S*>(a.face);
+  const uint32_t jk = uint32_t(j + N * k);
+#pragma unroll
+  for (int d = 1; d < 19; ++d) {
+    if (ex(d) == 1 && i0 == N - W) Form<S>::st(f + (uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk, h[d][W - 1]);
+    if (ex(d) == -1 && i0 == 0) Form<S>::st(f + (uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk, h[d][0]);
+  }
+}
+
+// ---- packed FP16 launches (8 cells per lane as 4 registers of half pairs) --
+//
+// Register r of direction A holds cells 2r (low half) and 2r + 1 (high
+// half) of the lane's row segment, as in the two-buffer sweep's packed path;
+// a shift by one cell is a 16-bit funnel shift of neighbouring registers,
+// the register across the lane boundary coming from a DPP move.  Each pair
+// is unpacked to FP32 for its collision, exactly as the two-buffer sweep
+// does, so both round identically.
+
+template <bool TRT>
+__device__ __forceinline__ void collide_h8(const InplaceArgs& a, uint32_t (*q)[4]) {
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    float h[19][2];
+#pragma unroll
+    for (int d = 0; d < 19; ++d) h[d][0] = half_lo(q[d][p]), h[d][1] = half_hi(q[d][p]);
+    icollide<__half, TRT>(a, h, 0);
+    icollide<__half, TRT>(a, h, 1);
+#pragma unroll
+    for (int d = 0; d < 19; ++d) q[d][p] = pack_pair(h[d][0], h[d][1]);
+  }
+}
+
+// the 8 cells shifted by one position: EX = +1 gives position c the cell
+// c - 1 (position 0 from `in`, the previous lane's last register), EX = -1
+// the cell c + 1 (position 7 from `in`, the next lane's first register)
+template <int EX>
+__device__ __forceinline__ void shift_h8(const uint32_t* q, uint32_t in, uint32_t* o) {
+  if constexpr (EX == 1) {
+    o[3] = funnel16(q[3], q[2]);
+    o[2] = funnel16(q[2], q[1]);
+    o[1] = funnel16(q[1], q[0]);
+    o[0] = funnel16(q[0], in);
+  } else {
+    o[0] = funnel16(q[1], q[0]);
+    o[1] = funnel16(q[2], q[1]);
+    o[2] = funnel16(q[3], q[2]);
+    o[3] = funnel16(in, q[3]);
+  }
+}
+
+template <int N, int A>
+__device__ __forceinline__ void odd_issue_h8(const InplaceArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
+                                             uint32_t (*q)[4], uint32_t* edge, uint32_t& wall) {
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  const int sy = j - EY, sz = k - EZ;
+  const bool by = outside<N>(sy), bz = outside<N>(sz);
+  const uint32_t row = uint32_t(N * ((sy & (N - 1)) + N * (sz & (N - 1))));
+  const int nbm = pick<0, -EY, -EZ>(sc, false, by, bz);
+  wall |= uint32_t(nbm < 0) << A;
+  const uint16_t* __restrict__ buf = static_cast<const uint16_t*>(a.buf);
+  const uint4 v =
+      *reinterpret_cast<const uint4*>(buf + pdf_index<N>(opp(A), uint32_t(nbm >= 0 ? nbm : slot), row + uint32_t(i0)));
+  q[A][0] = v.x, q[A][1] = v.y, q[A][2] = v.z, q[A][3] = v.w;
+  if constexpr (EX != 0) {
+    const bool at_end = EX == 1 ? i0 == 0 : i0 == N - 8;
+    const int nbx = pick<-EX, -EY, -EZ>(sc, true, by, bz);
+    wall |= uint32_t(at_end && nbx < 0) << A;
+    const int eb = nbx >= 0 ? nbx : slot;
+    edge[xdir_index(A)] = static_cast<const uint16_t*>(a.face)[xface_index<N, A>(uint32_t(eb), row / N)];
+  }
+}
+
+template <int N, int A = 0>
+__device__ __forceinline__ void odd_issue_all_h8(const InplaceArgs& a, const SlotCache& sc, int slot, int i0, int j,
+                                                 int k, uint32_t (*q)[4], uint32_t* edge, uint32_t& wall) {
+  odd_issue_h8<N, A>(a, sc, slot, i0, j, k, q, edge, wall);
+  if constexpr (A + 1 < 19) odd_issue_all_h8<N, A + 1>(a, sc, slot, i0, j, k, q, edge, wall);
+}
+
+template <int N, int A = 0>
+__device__ __forceinline__ void odd_shift_all_h8(int i0, uint32_t (*q)[4], const uint32_t* edge) {
+  constexpr int EX = ex(A);
+  if constexpr (EX == 1) {  // cell c takes cell c - 1
+    const uint32_t prev = dpp_move_u32<kDppRowShr1>(q[A][3]);
+    uint32_t o[4];
+    shift_h8<1>(q[A], i0 == 0 ? edge[xdir_index(A)] << 16 : prev, o);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) q[A][r] = o[r];
+  } else if constexpr (EX == -1) {  // cell c takes cell c + 1
+    const uint32_t next = dpp_move_u32<kDppRowShl1>(q[A][0]);
+    uint32_t o[4];
+    shift_h8<-1>(q[A], i0 == N - 8 ? edge[xdir_index(A)] : next, o);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) q[A][r] = o[r];
+  }
+  if constexpr (A + 1 < 19) odd_shift_all_h8<N, A + 1>(i0, q, edge);
+}
+
+// sources beyond a wall: the cell's own (x, A) in the swapped layout
+template <int N, int A = 1>
+__device__ __forceinline__ void odd_walls_h8(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0,
+                                             int j, int k, uint32_t wall, uint32_t (*q)[4]) {
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  if ((wall >> A) & 1u) {
+    const int sy = j - EY, sz = k - EZ;
+    const bool by = outside<N>(sy), bz = outside<N>(sz);
+    const uint16_t* __restrict__ own =
+        static_cast<const uint16_t*>(a.buf) + pdf_index<N>(A, uint32_t(slot), uint32_t(cell0));
+    if (pick<0, -EY, -EZ>(sc, false, by, bz) < 0) {
+      const uint4 v = *reinterpret_cast<const uint4*>(own);
+      q[A][0] = v.x, q[A][1] = v.y, q[A][2] = v.z, q[A][3] = v.w;
+    } else if constexpr (EX != 0) {
+      const bool at_end = EX == 1 ? i0 == 0 : i0 == N - 8;
+      if (at_end && pick<-EX, -EY, -EZ>(sc, true, by, bz) < 0) {
+        if (EX == 1)
+          q[A][0] = (q[A][0] & 0xFFFF0000u) | uint32_t(own[0]);
+        else
+          q[A][3] = (q[A][3] & 0xFFFFu) | (uint32_t(own[7]) << 16);
+      }
+    }
+  }
+  if constexpr (A + 1 < 19) odd_walls_h8<N, A + 1>(a, sc, slot, cell0, i0, j, k, wall, q);
+}
+
+__device__ __forceinline__ void store_u32x4(uint16_t* p, const uint32_t* o) {
+  const u32x4 t = {o[0], o[1], o[2], o[3]};
+  __builtin_nontemporal_store(t, reinterpret_cast<u32x4*>(p));
+}
+
+template <int N, int A>
+__device__ __forceinline__ void odd_store_h8(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0, int j,
+                                             int k, uint32_t (*q)[4]) {
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  uint16_t* __restrict__ buf = static_cast<uint16_t*>(a.buf);
+  const int dy = j + EY, dz = k + EZ;
+  const bool by = outside<N>(dy), bz = outside<N>(dz);
+  const uint32_t row = uint32_t(N * ((dy & (N - 1)) + N * (dz & (N - 1))));
+  const int nbd = pick<0, EY, EZ>(sc, false, by, bz);
+  uint16_t* __restrict__ own = buf + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(cell0));
+  uint32_t o[4];
+  if constexpr (EX == 1) {
+    shift_h8<1>(q[A], dpp_move_u32<kDppRowShr1>(q[A][3]), o);
+  } else if constexpr (EX == -1) {
+    shift_h8<-1>(q[A], dpp_move_u32<kDppRowShl1>(q[A][0]), o);
+  }
+  if (nbd < 0) {  // the whole destination row lies beyond a wall: every cell reflects
+    store_u32x4(own, q[A]);
+    return;
+  }
+  uint16_t* __restrict__ dst = buf + pdf_index<N>(A, uint32_t(nbd), row + uint32_t(i0));
+  if constexpr (EX == 0) {
+    store_u32x4(dst, q[A]);
+  } else {
+    const bool crossing_lane = EX == 1 ? i0 == 0 : i0 == N - 8;
+    if (!crossing_lane) {
+      store_u32x4(dst, o);
+    } else if (EX == 1) {  // positions 1 .. 7
+      dst[1] = uint16_t(o[0] >> 16);
+      *reinterpret_cast<uint32_t*>(dst + 2) = o[1];
+      *reinterpret_cast<uint2*>(dst + 4) = make_uint2(o[2], o[3]);
+    } else {  // positions 0 .. 6
+      *reinterpret_cast<uint2*>(dst) = make_uint2(o[0], o[1]);
+      *reinterpret_cast<uint32_t*>(dst + 4) = o[2];
+      dst[6] = uint16_t(o[3] & 0xFFFFu);
+    }
+    const bool leaving_lane = EX == 1 ? i0 == N - 8 : i0 == 0;
+    if (leaving_lane) {
+      const uint16_t end = EX == 1 ? uint16_t(q[A][3] >> 16) : uint16_t(q[A][0] & 0xFFFFu);
+      const int nbx = pick<EX, EY, EZ>(sc, true, by, bz);
+      if (nbx >= 0)
+        buf[pdf_index<N>(A, uint32_t(nbx), row + uint32_t(EX == 1 ? 0 : N - 1))] = end;
+      else
+        own[EX == 1 ? 7 : 0] = end;
+    }
+  }
+}
+
+template <int N, int A = 0>
+__device__ __forceinline__ void odd_store_all_h8(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0,
+                                                 int j, int k, uint32_t (*q)[4]) {
+  odd_store_h8<N, A>(a, sc, slot, cell0, i0, j, k, q);
+  if constexpr (A + 1 < 19) odd_store_all_h8<N, A + 1>(a, sc, slot, cell0, i0, j, k, q);
+}
+
+template <int N, bool TRT>
+__global__ void __launch_bounds__((IGeo<__half, N>::T)) inplace_odd_h8_kernel(InplaceArgs a) {
+  int slot, cell0;
+  tile_of<__half, N>(a, slot, cell0);
+  SlotCache sc;
+  load_table(a, slot, sc);
+  const int i0 = cell0 & (N - 1), j = (cell0 / N) & (N - 1), k = cell0 / (N * N);
+  uint32_t q[19][4];
+  uint32_t edge[kXDirs];
+  uint32_t wall = 0;
+  odd_issue_all_h8<N>(a, sc, slot, i0, j, k, q, edge, wall);
+  odd_shift_all_h8<N>(i0, q, edge);
+  if (wall) odd_walls_h8<N>(a, sc, slot, cell0, i0, j, k, wall, q);
+  collide_h8<TRT>(a, q);
+  odd_store_all_h8<N>(a, sc, slot, cell0, i0, j, k, q);
+}
+
+template <int N, bool TRT>
+__global__ void __launch_bounds__((IGeo<__half, N>::T)) inplace_even_h8_kernel(InplaceArgs a) {
+  constexpr int N3 = N * N * N;
+  int slot, cell0;
+  tile_of<__half, N>(a, slot, cell0);
+  const int i0 = cell0 & (N - 1), j = (cell0 / N) & (N - 1), k = cell0 / (N * N);
+  uint16_t* __restrict__ p = static_cast<uint16_t*>(a.buf) + pdf_index<N>(0, uint32_t(slot), uint32_t(cell0));
+  uint32_t q[19][4];
+#pragma unroll
+  for (int d = 0; d < 19; ++d) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p + d * N3);
+    q[d][0] = v.x, q[d][1] = v.y, q[d][2] = v.z, q[d][3] = v.w;
+  }
+  collide_h8<TRT>(a, q);
+#pragma unroll
+  for (int d = 0; d < 19; ++d) store_u32x4(p + opp(d) * N3, q[d]);
+  uint16_t* __restrict__ f = static_cast<uint16_t*>(a.face);
+  const uint32_t jk = uint32_t(j + N * k);
+#pragma unroll
+  for (int d = 1; d < 19; ++d) {
+    if (ex(d) == 1 && i0 == N - 8) f[(uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk] = uint16_t(q[d][3] >> 16);
+    if (ex(d) == -1 && i0 == 0) f[(uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk] = uint16_t(q[d][0] & 0xFFFFu);
+  }
+}
+
+// ---- layout conversions ------------------------------------------------------
+
+template <typename S>
+__global__ void inplace_swap_kernel(S* __restrict__ buf, int64_t ncells, int64_t n3) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= ncells) return;
+#pragma unroll
+  for (int a = 1; a < 19; a += 2) {
+    S* p = buf + pdf_at_rt(a, uint64_t(i), uint64_t(n3));
+    S* q = buf + pdf_at_rt(a + 1, uint64_t(i), uint64_t(n3));
+    const S t = *p;
+    *p = *q;
+    *q = t;
+  }
+}
+
+template <typename S>
+__global__ void inplace_pair_swap_kernel(S* __restrict__ buf, const int32_t* __restrict__ nbr, int64_t ncells, int n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= ncells) return;
+  const int64_t n3 = int64_t(n) * n * n;
+  const int64_t slot = i / n3;
+  const int cell = int(i - slot * n3);
+  const int x = cell % n, y = (cell / n) % n, z = cell / (n * n);
+  auto side = [n](int c) { return c < 0 ? -1 : (c >= n ? 1 : 0); };
+  for (int a = 1; a < 19; a += 2) {
+    const int sx = x - ex(a), sy = y - ey(a), sz = z - ez(a);
+    const int nb = nbr[slot * 27 + 13 + side(sx) + 3 * side(sy) + 9 * side(sz)];
+    if (nb < 0) continue;  // wall: the location keeps its value
+    const int sc = ((sx + n) % n) + n * (((sy + n) % n) + n * ((sz + n) % n));
+    S* p = buf + pdf_at_rt(a, uint64_t(i), uint64_t(n3));
+    S* q = buf + pdf_at_rt(opp(a), uint64_t(nb) * uint64_t(n3) + uint64_t(sc), uint64_t(n3));
+    const S t = *p;
+    *p = *q;
+    *q = t;
+  }
+}
+
+template <typename S>
+int64_t inplace_grid_t(int n, int64_t nblocks) {
+  switch (n) {
+    case 4: return nblocks * IGeo<S, 4>::TPB;
+    case 8: return nblocks * IGeo<S, 8>::TPB;
+    case 16: return nblocks * IGeo<S, 16>::TPB;
+    case 32: return nblocks * IGeo<S, 32>::TPB;
+    default: return -1;
+  }
+}
+
+template <typename S>
+hipError_t launch_inplace_t(int n, const InplaceArgs& a, bool odd, hipStream_t stream) {
+  auto go = [&](auto nn) -> hipError_t {
+    constexpr int N = decltype(nn)::value;
+    const int64_t grid = int64_t(a.nblocks) * IGeo<S, N>::TPB;
+    if (grid <= 0) return hipSuccess;
+    if (grid > int64_t(0x7FFFFFFF)) return hipErrorInvalidValue;
+    const dim3 g = dim3(unsigned(grid)), t = dim3(unsigned(IGeo<S, N>::T));
+    if constexpr (IGeo<S, N>::PACKED) {
+      if (odd) {
+        if (a.trt)
+          hipLaunchKernelGGL((inplace_odd_h8_kernel<N, true>), g, t, 0, stream, a);
+        else
+          hipLaunchKernelGGL((inplace_odd_h8_kernel<N, false>), g, t, 0, stream, a);
+      } else {
+        if (a.trt)
+          hipLaunchKernelGGL((inplace_even_h8_kernel<N, true>), g, t, 0, stream, a);
+        else
+          hipLaunchKernelGGL((inplace_even_h8_kernel<N, false>), g, t, 0, stream, a);
+      }
+      return hipGetLastError();
+    } else {
+      if (odd) {
+        if (a.trt)
+          hipLaunchKernelGGL((inplace_odd_kernel<S, N, true>), g, t, 0, stream, a);
+        else
+          hipLaunchKernelGGL((inplace_odd_kernel<S, N, false>), g, t, 0, stream, a);
+      } else {
+        if (a.trt)
+          hipLaunchKernelGGL((inplace_even_kernel<S, N, true>), g, t, 0, stream, a);
+        else
+          hipLaunchKernelGGL((inplace_even_kernel<S, N, false>), g, t, 0, stream, a);
+      }
+      return hipGetLastError();
+    }
+  };
+  switch (n) {
+    case 4: return go(std::integral_constant<int, 4>{});
+    case 8: return go(std::integral_constant<int, 8>{});
+    case 16: return go(std::integral_constant<int, 16>{});
+    case 32: return go(std::integral_constant<int, 32>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dev
+
+int64_t inplace_grid(int storage, int n, int64_t nblocks) {
+  switch (storage) {
+    case 0: return dev::inplace_grid_t<double>(n, nblocks);
+    case 1: return dev::inplace_grid_t<float>(n, nblocks);
+    case 2: return dev::inplace_grid_t<__half>(n, nblocks);
+    default: return -1;
+  }
+}
+
+hipError_t launch_inplace(int storage, int n, const InplaceArgs& a, bool odd, hipStream_t stream) {
+  switch (storage) {
+    case 0: return dev::launch_inplace_t<double>(n, a, odd, stream);
+    case 1: return dev::launch_inplace_t<float>(n, a, odd, stream);
+    case 2: return dev::launch_inplace_t<__half>(n, a, odd, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+namespace {
+constexpr int kConvThreads = 256;
+template <typename F>
+hipError_t by_storage(int storage, F&& f) {
+  switch (storage) {
+    case 0: return f(double{});
+    case 1: return f(float{});
+    case 2: return f(__half{});
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+hipError_t launch_inplace_swap(int storage, int n, void* buf, int64_t nblocks, hipStream_t stream) {
+  const int64_t n3 = int64_t(n) * n * n, ncells = nblocks * n3;
+  if (ncells <= 0) return hipSuccess;
+  const unsigned grid = unsigned((ncells + kConvThreads - 1) / kConvThreads);
+  return by_storage(storage, [&](auto s) -> hipError_t {
+    using S = decltype(s);
+    hipLaunchKernelGGL(dev::inplace_swap_kernel<S>, dim3(grid), dim3(kConvThreads), 0, stream, static_cast<S*>(buf),
+                       ncells, n3);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_inplace_pair_swap(int storage, int n, void* buf, const int32_t* nbr, int64_t nblocks,
+                                    hipStream_t stream) {
+  const int64_t ncells = nblocks * int64_t(n) * n * n;
+  if (ncells <= 0) return hipSuccess;
+  const unsigned grid = unsigned((ncells + kConvThreads - 1) / kConvThreads);
+  return by_storage(storage, [&](auto s) -> hipError_t {
+    using S = decltype(s);
+    hipLaunchKernelGGL(dev::inplace_pair_swap_kernel<S>, dim3(grid), dim3(kConvThreads), 0, stream,
+                       static_cast<S*>(buf), nbr, ncells, n);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace lbm

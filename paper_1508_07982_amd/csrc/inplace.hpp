@@ -1,0 +1,61 @@
+// In-place streaming (the AA pattern) for forests whose blocks all lie on
+// one level: one PDF buffer instead of two.
+//
+// Section 4.1 uses two grids (source and destination) and names the AA
+// pattern as the in-place alternative that refinement does not readily
+// admit.  Here it is built for forests without level interfaces.  The
+// buffer always holds the post-collision state f* of the last step, in one
+// of three layouts:
+//   natural: f*_a(x) at (x, a), the layout of the two-buffer path;
+//   swapped: f*_a(x) at (x, opp(a));
+//   pushed:  f*_a(x) at (x + e_a, a), the pre-collision value of the next
+//            step, or at (x, opp(a)) where x + e_a lies beyond a wall
+//            (halfway bounce-back, section 2.2).
+// The odd launch takes swapped to pushed: cell x reads f*_a(x - e_a) at
+// (x - e_a, opp(a)) (its own (x, a) where x - e_a is a wall), collides and
+// writes f*_a(x) to (x + e_a, a).  The even launch takes pushed to swapped:
+// cell x reads (x, a), collides and writes (x, opp(a)).  In both, every
+// memory location is read and then written by the one cell that owns it, so
+// the buffer is updated in place without races.  Both launches do the
+// two-buffer sweep's arithmetic on the same values, so results are bitwise
+// those of the two-buffer path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbm {
+
+enum InplaceLayout : int { kLayoutNatural = 0, kLayoutSwapped = 1, kLayoutPushed = 2 };
+
+struct InplaceArgs {
+  void* buf;             // the level's PDF buffer, block-major [slot][19][n^3]
+  void* face;            // x-face copy [slot][10][n^2]: written by the even launch, read by the odd one
+  const int32_t* nbr;    // [slot][27]: slot or kNbrWall
+  int32_t nblocks;
+  int32_t xcd;           // 1: work units grouped by XCD
+  int32_t trt;           // 1: TRT collision with a body force
+  float omega;           // omega (SRT) or lambda_e (TRT), FP32 arithmetic forms
+  float lambda_o;
+  float accel[3];
+  double omega64;        // the same for the FP64 form
+  double lambda_o64;
+  double accel64[3];
+};
+
+// Workgroups of one launch (each sweeps a tile of one block).
+int64_t inplace_grid(int storage, int n, int64_t nblocks);
+
+// odd = true: swapped -> pushed; false: pushed -> swapped.
+hipError_t launch_inplace(int storage, int n, const InplaceArgs& a, bool odd, hipStream_t stream);
+
+// natural <-> swapped: per cell, (x, a) <-> (x, opp(a)).
+hipError_t launch_inplace_swap(int storage, int n, void* buf, int64_t nblocks, hipStream_t stream);
+
+// pushed <-> swapped: (x, a) <-> (x - e_a, opp(a)) for every cell x and
+// direction a whose neighbour x - e_a is a cell (walls: fixed points).
+hipError_t launch_inplace_pair_swap(int storage, int n, void* buf, const int32_t* nbr, int64_t nblocks,
+                                    hipStream_t stream);
+
+}  // namespace lbm

@@ -106,6 +106,15 @@ static_assert(xdir_rt_matches(), "x directions");
 static_assert(xdir_dir(0) == 1 && xdir_dir(1) == 2 && xdir_dir(2) == 7 && xdir_dir(9) == 14, "x directions");
 
 // ---- storage forms --------------------------------------------------------
+// A value bound for FP16 storage is first rounded to FP32: without the empty
+// asm the compiler may fuse a collision's last multiply-add and the
+// conversion into one mixed-precision instruction (a single rounding) in one
+// kernel and not in another, and kernels that must agree bitwise would not.
+__device__ __forceinline__ float keep_fp32(float v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
 template <typename S>
 struct Form;
 template <>
@@ -130,7 +139,7 @@ template <>
 struct Form<__half> {
   using C = float;
   static __device__ __forceinline__ float ld(const __half* p) { return __half2float(*p); }
-  static __device__ __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(v); }
+  static __device__ __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(keep_fp32(v)); }
   static __device__ __forceinline__ float omega(const SweepArgs& a) { return a.omega; }
   static __device__ __forceinline__ float lambda_o(const SweepArgs& a) { return a.lambda_o; }
   static __device__ __forceinline__ float accel(const SweepArgs& a, int d) { return a.accel[d]; }
@@ -182,8 +191,10 @@ struct Vec<__half> {
   }
   static __device__ __forceinline__ void store(__half* p, const float* v) {
     u32x2 t;
-    t.x = uint32_t(__half_as_ushort(__float2half_rn(v[0]))) | (uint32_t(__half_as_ushort(__float2half_rn(v[1]))) << 16);
-    t.y = uint32_t(__half_as_ushort(__float2half_rn(v[2]))) | (uint32_t(__half_as_ushort(__float2half_rn(v[3]))) << 16);
+    t.x = uint32_t(__half_as_ushort(__float2half_rn(keep_fp32(v[0])))) |
+          (uint32_t(__half_as_ushort(__float2half_rn(keep_fp32(v[1])))) << 16);
+    t.y = uint32_t(__half_as_ushort(__float2half_rn(keep_fp32(v[2])))) |
+          (uint32_t(__half_as_ushort(__float2half_rn(keep_fp32(v[3])))) << 16);
     __builtin_nontemporal_store(t, reinterpret_cast<u32x2*>(p));
   }
 };

@@ -83,6 +83,9 @@ struct lbm_forest {
   int* d_err = nullptr;
   bool coal_check = false;                  // FP64 accumulation check of the coalescence
   bool interp = false;                      // interpolated explosion (lbm_set_explosion_interpolation)
+  bool inplace = false;                     // in-place streaming (lbm_set_inplace): level 0 keeps one buffer
+  int layout = 0;                           // its layout (InplaceLayout in inplace.hpp)
+  bool post_lost = false;                   // in-place steps left no state of the last step's start (regrid needs it)
   unsigned long long* d_check = nullptr;    // its figures (see CoalArgs::check)
   double* d_partials = nullptr;
   std::vector<void*> allocations;
@@ -104,5 +107,10 @@ inline const void* current_state(const lbm_forest* f, int L) { return f->lv[L].b
 
 // Sets the thread's error message and returns `code`.
 int set_error(int code, const char* fmt, ...);
+
+// Brings the state into the natural layout (f*_a(x) at (x, a)) before a
+// kernel other than the sweeps reads it: a no-op except with in-place
+// streaming, whose buffer may hold the swapped or pushed layout.
+int prepare_state_read(lbm_forest* f);
 
 }  // namespace lbm

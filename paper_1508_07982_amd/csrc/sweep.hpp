@@ -383,6 +383,7 @@ __device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, 
 // h + omega (h_eq - h) = (1 - omega) h + omega h_eq.
 template <typename C, int W, int A = 1>
 __device__ __forceinline__ void relax_pairs(C (*h)[W], int c, C base, C ux, C uy, C uz, C omc, C ow1, C ow2) {
+#pragma clang fp contract(on)
   const C ow = wgt<C>(A) == wgt<C>(1) ? ow1 : ow2;  // omega w_A
   C t = C(0);
   if constexpr (ex(A) != 0) t += ex(A) > 0 ? ux : -ux;
@@ -395,9 +396,13 @@ __device__ __forceinline__ void relax_pairs(C (*h)[W], int c, C base, C ux, C uy
   if constexpr (A + 2 < 19) relax_pairs<C, W, A + 2>(h, c, base, ux, uy, uz, omc, ow1, ow2);
 }
 
-// SRT collision of cell c in shifted form (rho0 = 1).
+// SRT collision of cell c in shifted form (rho0 = 1).  Multiply-adds are
+// fused only within one expression (contract(on)), so every kernel that
+// inlines the collision rounds it the same way: the in-place and the
+// two-buffer streaming give bitwise equal results.
 template <typename C, int W>
 __device__ __forceinline__ void collide(C (*h)[W], int c, C om) {
+#pragma clang fp contract(on)
   C drho = h[0][c], ux = C(0), uy = C(0), uz = C(0);
 #pragma unroll
   for (int a = 1; a < 19; a += 2) {  // opposite pairs (a, a + 1)
@@ -442,6 +447,7 @@ __device__ __forceinline__ void store_faces(const SweepArgs& a, int row, int i0,
 template <typename C, int W, int A = 1>
 __device__ __forceinline__ void relax_pairs_trt(C (*h)[W], int c, C base, C ux, C uy, C uz, C le, C lo, C ax, C ay,
                                                 C az) {
+#pragma clang fp contract(on)
   const C w = wgt<C>(A);
   C t = C(0), ta = C(0);
   if constexpr (ex(A) != 0) t += ex(A) > 0 ? ux : -ux, ta += ex(A) > 0 ? ax : -ax;
@@ -457,6 +463,7 @@ __device__ __forceinline__ void relax_pairs_trt(C (*h)[W], int c, C base, C ux, 
 }
 template <typename C, int W>
 __device__ __forceinline__ void collide_trt(C (*h)[W], int c, C le, C lo, C ax, C ay, C az) {
+#pragma clang fp contract(on)
   C drho = h[0][c], ux = C(0), uy = C(0), uz = C(0);
 #pragma unroll
   for (int a = 1; a < 19; a += 2) {
@@ -512,7 +519,7 @@ __device__ __forceinline__ void update_lane(const SweepArgs& a, const SlotCache&
 // storage would hold them.
 __device__ __forceinline__ float half_lo(uint32_t q) { return __half2float(__ushort_as_half(uint16_t(q & 0xFFFFu))); }
 __device__ __forceinline__ float half_hi(uint32_t q) { return __half2float(__ushort_as_half(uint16_t(q >> 16))); }
-__device__ __forceinline__ uint32_t half_bits(float v) { return uint32_t(__half_as_ushort(__float2half_rn(v))); }
+__device__ __forceinline__ uint32_t half_bits(float v) { return uint32_t(__half_as_ushort(__float2half_rn(keep_fp32(v)))); }
 __device__ __forceinline__ uint32_t pack_pair(float lo, float hi) { return half_bits(lo) | (half_bits(hi) << 16); }
 // (hi:lo) >> 16: the high half of lo and the low half of hi
 __device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) { return __builtin_amdgcn_alignbit(hi, lo, 16); }

@@ -75,6 +75,9 @@ _SIGNATURES = {
     "lbm_set_schedule": [ctypes.c_void_p, ctypes.c_int],
     "lbm_set_coalescence_check": [ctypes.c_void_p, ctypes.c_int],
     "lbm_set_explosion_interpolation": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_set_inplace": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_get_inplace": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_device_memory": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "lbm_coalescence_check": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_launch": [ctypes.c_void_p, ctypes.c_int],
     "lbm_synchronize": [ctypes.c_void_p],
@@ -284,6 +287,16 @@ class Forest:
     def set_explosion_interpolation(self, on: bool = True):
         """Limited linear reconstruction of exploded values (see the header)."""
         _check(self._lib.lbm_set_explosion_interpolation(self._h, int(bool(on))))
+
+    def set_inplace(self, on: bool = True):
+        """In-place (AA pattern) streaming on a forest whose leaves all lie
+        on level 0: one PDF buffer instead of two (see the header)."""
+        _check(self._lib.lbm_set_inplace(self._h, int(bool(on))))
+
+    def inplace(self) -> bool:
+        v = ctypes.c_int()
+        _check(self._lib.lbm_get_inplace(self._h, ctypes.byref(v)))
+        return bool(v.value)
 
     def set_coalescence_check(self, on: bool = True):
         _check(self._lib.lbm_set_coalescence_check(self._h, int(bool(on))))
@@ -505,6 +518,14 @@ class MLP:
         _check(self._lib.lbm_mlp_train(self._h, _ptr(X), _ptr(t), len(X), int(epochs), int(batch), float(lr),
                                        int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(losses)))
         return losses[:epochs]
+
+
+def device_memory(device: int = 0):
+    """(free bytes, total bytes) of a device (hipMemGetInfo)."""
+    lib = load_library()
+    fr, tot = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.lbm_device_memory(int(device), ctypes.byref(fr), ctypes.byref(tot)))
+    return fr.value, tot.value
 
 
 # ---- bandwidth probes (lbm_probe.h) ------------------------------------------

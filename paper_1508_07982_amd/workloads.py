@@ -123,6 +123,15 @@ def config_sphere(n: int = 32, roots: int = 4) -> Workload:
                     "%d^3 roots of %d^3 cells, sphere r=0.25 surface refined to level 3" % (R, n))
 
 
+def config_uniform(n: int = 32, roots: int = 16) -> Workload:
+    """Periodic cube of roots^3 blocks of n^3 cells on one level (no
+    refinement): 512^3 cells with the defaults.  omega0 = 1.9, Taylor-Green
+    amplitude 0.02 plus noise +-1e-4.  The grid for comparing two-buffer and
+    in-place streaming."""
+    return Workload("uniform_n%d_R%d" % (n, roots), roots, n, 0, 1.9, None, "taylor_green", 0.02, 1e-4, 3, 20,
+                    "%d^3 roots of %d^3 cells, one level" % (roots, n))
+
+
 def config_slab_sphere(n: int = 16, roots: int = 5) -> Workload:
     """About 8.5 M cells over 4 levels in 16^3 blocks: refinement along a
     thin plate and a small sphere surface (seeded positions), omega0 = 1.9."""
