@@ -363,6 +363,7 @@ InplaceArgs inplace_args(const lbm_forest* f) {
   InplaceArgs a;
   a.buf = v.buf[0];
   a.face = v.xface[0];
+  a.entry = v.xface[1];  // the second x-face buffer serves as the entry buffer
   a.nbr = v.nbr;
   a.nblocks = v.nblocks;
   a.xcd = v.order;
@@ -453,7 +454,10 @@ void* current_buffer_mut(lbm_forest* f, int L) { return f->lv[L].buf[f->rot[L]];
 int lbm::prepare_state_read(lbm_forest* f) {
   if (!f->inplace || f->layout == kLayoutNatural) return LBM_OK;
   const LevelDev& v = f->lv[0];
-  if (f->layout == kLayoutPushed) HIP_TRY(launch_inplace_pair_swap(f->storage, f->n, v.buf[0], v.nbr, v.nblocks, f->stream));
+  if (f->layout == kLayoutPushed) {
+    HIP_TRY(launch_inplace_entry_merge(f->storage, f->n, v.buf[0], v.xface[1], v.nblocks, f->stream));
+    HIP_TRY(launch_inplace_pair_swap(f->storage, f->n, v.buf[0], v.nbr, v.nblocks, f->stream));
+  }
   HIP_TRY(launch_inplace_swap(f->storage, f->n, v.buf[0], v.nblocks, f->stream));
   f->layout = kLayoutNatural;
   return LBM_OK;
@@ -760,13 +764,11 @@ int lbm_set_inplace(lbm_forest* f, int on) {
       f->rot[0] = 0;
     }
     f->rot_prev = f->rot;
-    for (void* p : {v.buf[1], v.xface[1]}) {
-      auto it = std::find(v.allocs.begin(), v.allocs.end(), p);
-      if (it != v.allocs.end()) v.allocs.erase(it);
-      if (p) HIP_TRY(hipFree(p));
-    }
+    // the second PDF buffer goes; its x-face buffer stays as the entry buffer
+    auto it = std::find(v.allocs.begin(), v.allocs.end(), v.buf[1]);
+    if (it != v.allocs.end()) v.allocs.erase(it);
+    if (v.buf[1]) HIP_TRY(hipFree(v.buf[1]));
     v.buf[1] = nullptr;
-    v.xface[1] = nullptr;
     v.nbuf = 1;
     f->inplace = true;
     f->layout = kLayoutNatural;
@@ -777,8 +779,6 @@ int lbm_set_inplace(lbm_forest* f, int on) {
     uint8_t* p = nullptr;
     if ((rc = dev_alloc(v.allocs, &p, size_t(v.plane) * 19 * sb))) return rc;
     v.buf[1] = p;
-    if ((rc = dev_alloc(v.allocs, &p, size_t(v.nblocks) * 10 * f->n * f->n * sb))) return rc;
-    v.xface[1] = p;
     v.nbuf = 2;
     HIP_TRY(launch_face_copy(f->storage, f->n, v.buf[0], v.xface[0], v.nblocks, f->stream));
     HIP_TRY(hipStreamSynchronize(f->stream));

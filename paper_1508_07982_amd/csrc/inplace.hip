@@ -11,9 +11,9 @@
 // block (found in the scalar neighbour table), rows shifted in x come from
 // the adjacent lane, and at a block's x face one element per row end
 // crosses to the x neighbour: read from the x-face copy that the even
-// launch wrote, written as a single element.  The first lane of a row
-// (e_x = +1) or the last (e_x = -1) leaves the crossing position to the x
-// neighbour's workgroup and stores the rest of its vector element-wise.
+// launch wrote, and written to the entry buffer (same layout), which the
+// even launch reads for the cells at x faces.  Every buffer row is then
+// written with whole vectors.
 #include "inplace.hpp"
 #include "sweep.hpp"
 
@@ -132,8 +132,8 @@ __device__ __forceinline__ void odd_shift_all(int i0, typename Form<S>::C (*h)[I
 }
 
 // Sources beyond a wall: the cell's own post-collision value of the
-// opposite direction, f*_opp(A)(x), which the swapped layout keeps at
-// (x, A) (halfway bounce-back).
+// opposite direction, f*_opp(A)(x) (halfway bounce-back), which the swapped
+// layout keeps at (x, A), and the x-face copy too where x is at an x face.
 template <typename S, int N, int A = 1>
 __device__ __forceinline__ void odd_walls(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0, int j,
                                           int k, uint32_t wall, typename Form<S>::C (*h)[IGeo<S, N>::W]) {
@@ -150,27 +150,40 @@ __device__ __forceinline__ void odd_walls(const InplaceArgs& a, const SlotCache&
       if (at_end && pick<-EX, -EY, -EZ>(sc, true, by, bz) < 0) cells = EX == 1 ? 1u : 1u << (W - 1);
     }
     const S* __restrict__ own = static_cast<const S*>(a.buf) + pdf_index<N>(A, uint32_t(slot), uint32_t(cell0));
+    if (cells == (1u << W) - 1u) {
 #pragma unroll
-    for (int c = 0; c < W; ++c)
-      if ((cells >> c) & 1u) h[A][c] = Form<S>::ld(own + c);
+      for (int c = 0; c < W; ++c) h[A][c] = Form<S>::ld(own + c);
+    } else if constexpr (EX != 0) {
+      // the end cell at an x wall: its own value leaving through that face,
+      // from the x-face copy (in the buffer, an x-crossing push of another
+      // row may overwrite that location during this launch)
+      if (cells)
+        h[A][EX == 1 ? 0 : W - 1] =
+            Form<S>::ld(static_cast<const S*>(a.face) + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)));
+    }
   }
   if constexpr (A + 1 < 19) odd_walls<S, N, A + 1>(a, sc, slot, cell0, i0, j, k, wall, h);
 }
 
 // Store direction A: f*_A(x) to (x + e_A, A), or to (x, opp(A)) where x + e_A
-// lies beyond a wall.
+// lies beyond a wall.  A value entering a block through an x face (cell
+// x = 0 with e_A,x = +1, x = n - 1 with e_A,x = -1) goes to the entry buffer
+// instead; the lane that would write it into the buffer's row writes its
+// whole vector, the entering position included, which then holds no value.
 template <typename S, int N, int A>
 __device__ __forceinline__ void odd_store(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0, int j,
                                           int k, typename Form<S>::C (*h)[IGeo<S, N>::W]) {
   using C = typename Form<S>::C;
   constexpr int W = IGeo<S, N>::W;
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  constexpr int END = EX == 1 ? W - 1 : 0;  // the cell that leaves through the x face
   S* __restrict__ buf = static_cast<S*>(a.buf);
+  S* __restrict__ entry = static_cast<S*>(a.entry);
   const int dy = j + EY, dz = k + EZ;
   const bool by = outside<N>(dy), bz = outside<N>(dz);
   const uint32_t row = uint32_t(N * ((dy & (N - 1)) + N * (dz & (N - 1))));
   const int nbd = pick<0, EY, EZ>(sc, false, by, bz);
-  S* __restrict__ own = buf + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(cell0));
+  const bool leaving_lane = EX == 1 ? i0 == N - W : i0 == 0;
   // x shift of the row by one cell (DPP, every lane takes part)
   C v[W];
   if constexpr (EX == 1) {
@@ -185,31 +198,23 @@ __device__ __forceinline__ void odd_store(const InplaceArgs& a, const SlotCache&
     v[W - 1] = next;
   }
   if (nbd < 0) {  // the whole destination row lies beyond a wall: every cell reflects
-    Vec<S>::store(own, h[A]);
+    Vec<S>::store(buf + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(cell0)), h[A]);
+    if constexpr (EX != 0)
+      if (leaving_lane)  // the end cell's reflection enters through its own x face
+        Form<S>::st(entry + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)), h[A][END]);
     return;
   }
   S* __restrict__ dst = buf + pdf_index<N>(A, uint32_t(nbd), row + uint32_t(i0));
   if constexpr (EX == 0) {
     Vec<S>::store(dst, h[A]);
   } else {
-    constexpr int KEEP = EX == 1 ? 0 : W - 1;  // position owned by the x neighbour's end cell
-    const bool crossing_lane = EX == 1 ? i0 == 0 : i0 == N - W;
-    if (crossing_lane) {
-#pragma unroll
-      for (int c = 0; c < W; ++c)
-        if (c != KEEP) Form<S>::st(dst + c, v[c]);
-    } else {
-      Vec<S>::store(dst, v);
-    }
-    // the end cell whose destination lies in the x neighbour (or beyond a wall)
-    const bool leaving_lane = EX == 1 ? i0 == N - W : i0 == 0;
+    Vec<S>::store(dst, v);
     if (leaving_lane) {
-      constexpr int END = EX == 1 ? W - 1 : 0;
       const int nbx = pick<EX, EY, EZ>(sc, true, by, bz);
       if (nbx >= 0)
-        Form<S>::st(buf + pdf_index<N>(A, uint32_t(nbx), row + uint32_t(EX == 1 ? 0 : N - 1)), h[A][END]);
-      else
-        Form<S>::st(own + END, h[A][END]);
+        Form<S>::st(entry + xface_index<N, A>(uint32_t(nbx), row / N), h[A][END]);
+      else  // an x wall: the reflection enters through the cell's own face
+        Form<S>::st(entry + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)), h[A][END]);
     }
   }
 }
@@ -254,6 +259,15 @@ __global__ void __launch_bounds__((IGeo<S, N>::T)) inplace_even_kernel(InplaceAr
   C h[19][W];
 #pragma unroll
   for (int d = 0; d < 19; ++d) Vec<S>::load(p + d * N3, h[d]);
+  // values that entered through an x face come from the entry buffer
+  const S* __restrict__ e = static_cast<const S*>(a.entry);
+  const uint32_t jk0 = uint32_t(j + N * k);
+#pragma unroll
+  for (int d = 1; d < 19; ++d) {
+    if (ex(d) == 1 && i0 == 0) h[d][0] = Form<S>::ld(e + (uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk0);
+    if (ex(d) == -1 && i0 == N - W)
+      h[d][W - 1] = Form<S>::ld(e + (uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk0);
+  }
 #pragma unroll
   for (int c = 0; c < W; ++c) icollide<S, TRT>(a, h, c);
 #pragma unroll
@@ -373,11 +387,13 @@ __device__ __forceinline__ void odd_walls_h8(const InplaceArgs& a, const SlotCac
       q[A][0] = v.x, q[A][1] = v.y, q[A][2] = v.z, q[A][3] = v.w;
     } else if constexpr (EX != 0) {
       const bool at_end = EX == 1 ? i0 == 0 : i0 == N - 8;
-      if (at_end && pick<-EX, -EY, -EZ>(sc, true, by, bz) < 0) {
+      if (at_end && pick<-EX, -EY, -EZ>(sc, true, by, bz) < 0) {  // from the x-face copy (see odd_walls)
+        const uint32_t v =
+            static_cast<const uint16_t*>(a.face)[xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))];
         if (EX == 1)
-          q[A][0] = (q[A][0] & 0xFFFF0000u) | uint32_t(own[0]);
+          q[A][0] = (q[A][0] & 0xFFFF0000u) | v;
         else
-          q[A][3] = (q[A][3] & 0xFFFFu) | (uint32_t(own[7]) << 16);
+          q[A][3] = (q[A][3] & 0xFFFFu) | (v << 16);
       }
     }
   }
@@ -394,11 +410,13 @@ __device__ __forceinline__ void odd_store_h8(const InplaceArgs& a, const SlotCac
                                              int k, uint32_t (*q)[4]) {
   constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
   uint16_t* __restrict__ buf = static_cast<uint16_t*>(a.buf);
+  uint16_t* __restrict__ entry = static_cast<uint16_t*>(a.entry);
   const int dy = j + EY, dz = k + EZ;
   const bool by = outside<N>(dy), bz = outside<N>(dz);
   const uint32_t row = uint32_t(N * ((dy & (N - 1)) + N * (dz & (N - 1))));
   const int nbd = pick<0, EY, EZ>(sc, false, by, bz);
-  uint16_t* __restrict__ own = buf + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(cell0));
+  const bool leaving_lane = EX == 1 ? i0 == N - 8 : i0 == 0;
+  const uint16_t end = EX == 1 ? uint16_t(q[A][3] >> 16) : uint16_t(q[A][0] & 0xFFFFu);
   uint32_t o[4];
   if constexpr (EX == 1) {
     shift_h8<1>(q[A], dpp_move_u32<kDppRowShr1>(q[A][3]), o);
@@ -406,33 +424,22 @@ __device__ __forceinline__ void odd_store_h8(const InplaceArgs& a, const SlotCac
     shift_h8<-1>(q[A], dpp_move_u32<kDppRowShl1>(q[A][0]), o);
   }
   if (nbd < 0) {  // the whole destination row lies beyond a wall: every cell reflects
-    store_u32x4(own, q[A]);
+    store_u32x4(buf + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(cell0)), q[A]);
+    if constexpr (EX != 0)
+      if (leaving_lane) entry[xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))] = end;
     return;
   }
   uint16_t* __restrict__ dst = buf + pdf_index<N>(A, uint32_t(nbd), row + uint32_t(i0));
   if constexpr (EX == 0) {
     store_u32x4(dst, q[A]);
   } else {
-    const bool crossing_lane = EX == 1 ? i0 == 0 : i0 == N - 8;
-    if (!crossing_lane) {
-      store_u32x4(dst, o);
-    } else if (EX == 1) {  // positions 1 .. 7
-      dst[1] = uint16_t(o[0] >> 16);
-      *reinterpret_cast<uint32_t*>(dst + 2) = o[1];
-      *reinterpret_cast<uint2*>(dst + 4) = make_uint2(o[2], o[3]);
-    } else {  // positions 0 .. 6
-      *reinterpret_cast<uint2*>(dst) = make_uint2(o[0], o[1]);
-      *reinterpret_cast<uint32_t*>(dst + 4) = o[2];
-      dst[6] = uint16_t(o[3] & 0xFFFFu);
-    }
-    const bool leaving_lane = EX == 1 ? i0 == N - 8 : i0 == 0;
+    store_u32x4(dst, o);
     if (leaving_lane) {
-      const uint16_t end = EX == 1 ? uint16_t(q[A][3] >> 16) : uint16_t(q[A][0] & 0xFFFFu);
       const int nbx = pick<EX, EY, EZ>(sc, true, by, bz);
       if (nbx >= 0)
-        buf[pdf_index<N>(A, uint32_t(nbx), row + uint32_t(EX == 1 ? 0 : N - 1))] = end;
+        entry[xface_index<N, A>(uint32_t(nbx), row / N)] = end;
       else
-        own[EX == 1 ? 7 : 0] = end;
+        entry[xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))] = end;
     }
   }
 }
@@ -473,6 +480,15 @@ __global__ void __launch_bounds__((IGeo<__half, N>::T)) inplace_even_h8_kernel(I
   for (int d = 0; d < 19; ++d) {
     const uint4 v = *reinterpret_cast<const uint4*>(p + d * N3);
     q[d][0] = v.x, q[d][1] = v.y, q[d][2] = v.z, q[d][3] = v.w;
+  }
+  const uint16_t* __restrict__ e = static_cast<const uint16_t*>(a.entry);
+  const uint32_t jk0 = uint32_t(j + N * k);
+#pragma unroll
+  for (int d = 1; d < 19; ++d) {  // values that entered through an x face
+    if (ex(d) == 1 && i0 == 0)
+      q[d][0] = (q[d][0] & 0xFFFF0000u) | uint32_t(e[(uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk0]);
+    if (ex(d) == -1 && i0 == N - 8)
+      q[d][3] = (q[d][3] & 0xFFFFu) | (uint32_t(e[(uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk0]) << 16);
   }
   collide_h8<TRT>(a, q);
 #pragma unroll
@@ -522,6 +538,20 @@ __global__ void inplace_pair_swap_kernel(S* __restrict__ buf, const int32_t* __r
     *p = *q;
     *q = t;
   }
+}
+
+// Entry buffer -> buffer: the values that entered through x faces, back
+// into their places (before the pushed layout is converted).
+template <typename S>
+__global__ void inplace_entry_merge_kernel(S* __restrict__ buf, const S* __restrict__ entry, int64_t count, int n) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const int64_t n2 = int64_t(n) * n;
+  const int64_t slot = e / (kXDirs * n2);
+  const int a = xdir_dir(int((e / n2) % kXDirs));
+  const int64_t jk = e % n2;
+  const int x = ex(a) > 0 ? 0 : n - 1;
+  buf[pdf_at_rt(a, uint64_t(slot) * uint64_t(n2 * n) + uint64_t(x + n * jk), uint64_t(n2 * n))] = entry[e];
 }
 
 template <typename S>
@@ -621,6 +651,19 @@ hipError_t launch_inplace_swap(int storage, int n, void* buf, int64_t nblocks, h
     using S = decltype(s);
     hipLaunchKernelGGL(dev::inplace_swap_kernel<S>, dim3(grid), dim3(kConvThreads), 0, stream, static_cast<S*>(buf),
                        ncells, n3);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_inplace_entry_merge(int storage, int n, void* buf, const void* entry, int64_t nblocks,
+                                      hipStream_t stream) {
+  const int64_t count = nblocks * dev::kXDirs * int64_t(n) * n;
+  if (count <= 0) return hipSuccess;
+  const unsigned grid = unsigned((count + kConvThreads - 1) / kConvThreads);
+  return by_storage(storage, [&](auto s) -> hipError_t {
+    using S = decltype(s);
+    hipLaunchKernelGGL(dev::inplace_entry_merge_kernel<S>, dim3(grid), dim3(kConvThreads), 0, stream,
+                       static_cast<S*>(buf), static_cast<const S*>(entry), count, n);
     return hipGetLastError();
   });
 }

@@ -10,7 +10,10 @@
 //   swapped: f*_a(x) at (x, opp(a));
 //   pushed:  f*_a(x) at (x + e_a, a), the pre-collision value of the next
 //            step, or at (x, opp(a)) where x + e_a lies beyond a wall
-//            (halfway bounce-back, section 2.2).
+//            (halfway bounce-back, section 2.2); a value whose place is a
+//            cell at an x face that it enters through (x = 0 for
+//            e_a,x = +1, x = n - 1 for e_a,x = -1) is held in the entry
+//            buffer (x-face layout) instead.
 // The odd launch takes swapped to pushed: cell x reads f*_a(x - e_a) at
 // (x - e_a, opp(a)) (its own (x, a) where x - e_a is a wall), collides and
 // writes f*_a(x) to (x + e_a, a).  The even launch takes pushed to swapped:
@@ -32,6 +35,7 @@ enum InplaceLayout : int { kLayoutNatural = 0, kLayoutSwapped = 1, kLayoutPushed
 struct InplaceArgs {
   void* buf;             // the level's PDF buffer, block-major [slot][19][n^3]
   void* face;            // x-face copy [slot][10][n^2]: written by the even launch, read by the odd one
+  void* entry;           // entry buffer [slot][10][n^2]: written by the odd launch, read by the even one
   const int32_t* nbr;    // [slot][27]: slot or kNbrWall
   int32_t nblocks;
   int32_t xcd;           // 1: work units grouped by XCD
@@ -52,6 +56,11 @@ hipError_t launch_inplace(int storage, int n, const InplaceArgs& a, bool odd, hi
 
 // natural <-> swapped: per cell, (x, a) <-> (x, opp(a)).
 hipError_t launch_inplace_swap(int storage, int n, void* buf, int64_t nblocks, hipStream_t stream);
+
+// Pushed layout: the entry buffer's values back into the buffer (before
+// launch_inplace_pair_swap converts it).
+hipError_t launch_inplace_entry_merge(int storage, int n, void* buf, const void* entry, int64_t nblocks,
+                                      hipStream_t stream);
 
 // pushed <-> swapped: (x, a) <-> (x - e_a, opp(a)) for every cell x and
 // direction a whose neighbour x - e_a is a cell (walls: fixed points).
