@@ -216,6 +216,31 @@ def inplace_form(torch, lbm, W, stream, storage):
     return out
 
 
+def inplace_refined_form(torch, lbm, W, w, stream, storage, steps):
+    """The benchmark grid with its finest level streamed in place: MLUPS,
+    per-level table and the device memory of the forest before and after
+    switching in-place streaming on."""
+    torch.cuda.synchronize()
+    free0, _ = lbm.device_memory(0)
+    g = make_forest(lbm, W, w, storage, stream.cuda_stream)
+    g.synchronize()
+    free1, _ = lbm.device_memory(0)
+    g.set_inplace(True)
+    free2, _ = lbm.device_memory(0)
+    g.step_coarse(2)
+    ms = timed_steps(torch, g, stream, steps)
+    sweeps, coal = g.time_launches(1)
+    upd = g.updates_per_coarse_step()
+    out = {"MLUPS": round(upd / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4), "steps": steps,
+           "device_bytes_two_buffer": int(free0 - free1), "device_bytes_in_place": int(free0 - free2),
+           "device_bytes_ratio": round((free0 - free2) / (free0 - free1), 4),
+           "per_level": level_table(g, sweeps, BYTES[storage], coal)}
+    g.close()
+    del g
+    torch.cuda.synchronize()
+    return out
+
+
 def ceilings_now(torch, lbm):
     """The copy probe and the sweep-shape probe at the finest level's size
     (FP64 elements, 2368 blocks of 32^3 cells), measured in this run."""
@@ -350,6 +375,10 @@ def main():
                                          "ms_per_step": round(msp, 3)}
         gp.close()
         del gp
+        for storage in ("f64", "f32"):
+            forms[f"{storage}_inplace_finest_graph"] = inplace_refined_form(torch, lbm, W, w, stream, storage, 5)
+            print(f"{storage} finest level in place: {forms[storage + '_inplace_finest_graph']['MLUPS']} MLUPS",
+                  file=sys.stderr, flush=True)
         for storage in ("f64", "f32", "f16"):
             forms[f"{storage}_inplace_uniform"] = inplace_form(torch, lbm, W, stream, storage)
             print(f"{storage} in place: {forms[storage + '_inplace_uniform']['in_place']['MLUPS']} MLUPS",

@@ -165,7 +165,7 @@ void set_level_omegas(lbm_forest* f);
 int refresh_faces(lbm_forest* f) {
   for (size_t L = 0; L < f->lv.size(); ++L) {
     const LevelDev& v = f->lv[L];
-    const int b = f->rot[L];
+    const int b = current_index(f, int(L));
     HIP_TRY(launch_face_copy(f->storage, f->n, v.buf[b], v.xface[b], v.nblocks, f->stream));
   }
   return LBM_OK;
@@ -183,9 +183,12 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
           std::vector<Op>& ops) {
   const LevelDev& d = f->lv[L];
   const int nlev = int(f->lv.size());
+  const bool aa = f->inplace && f->inplace_level > 0 && L == f->inplace_level;  // refined, in place
   const void* prev = nullptr;
   int cb, nb;  // buffers read and written
-  if (L == 0) {
+  if (aa) {
+    cb = nb = 0;
+  } else if (L == 0) {
     cb = r[0];
     nb = r[0] ^ 1;
   } else if (substep == 1) {
@@ -202,15 +205,25 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   const void* fine1 = nullptr;
   const void* fine0_x = nullptr;
   const void* fine1_x = nullptr;
+  const void* save_t = nullptr;
+  const void* save_half = nullptr;
   if (L + 1 < nlev) {
     const int rf = r[L + 1];
     emit(f, L + 1, 1, r, cur, ops);
     emit(f, L + 1, 2, r, cur, ops);
     const LevelDev& fd = f->lv[L + 1];
-    fine0 = fd.buf[rf];
-    fine1 = fd.buf[(rf + 1) % 3];
-    fine0_x = fd.xface[rf];
-    fine1_x = fd.xface[(rf + 1) % 3];
+    if (f->inplace && L + 1 == f->inplace_level) {
+      // the finer level in place: its states at t and t + 1/2 come from its saves
+      fine0 = fine1 = fd.buf[0];
+      fine0_x = fine1_x = fd.xface[0];
+      save_t = f->save[rf];
+      save_half = f->save[2];
+    } else {
+      fine0 = fd.buf[rf];
+      fine1 = fd.buf[(rf + 1) % 3];
+      fine0_x = fd.xface[rf];
+      fine1_x = fd.xface[(rf + 1) % 3];
+    }
   }
   Op op;
   op.level = L;
@@ -268,13 +281,49 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
     c.coal.err = f->d_err;
     c.coal.interp = f->interp ? 1 : 0;
     c.coal.walls = f->forest.periodic[0] && f->forest.periodic[1] && f->forest.periodic[2] ? 0 : 1;
+    c.coal.save_t = save_t;
+    c.coal.save_half = save_half;
     ops.push_back(c);
   }
+  if (aa) {
+    // the first substep is the odd launch, the second the even one; the
+    // rotation entry is the parity q of the level's parent steps: saves at t
+    // in save[q], at t + 1 into save[q ^ 1], at t + 1/2 in save[2]
+    const int q = r[L] & 1;
+    op.kind = Op::kInplace;
+    op.odd = substep == 1 ? 1 : 0;
+    InplaceArgs& ia = op.ia;
+    ia = InplaceArgs{};
+    ia.buf = d.buf[0];
+    ia.face = d.xface[0];
+    ia.entry = d.xface[1];
+    ia.nbr = d.nbr;
+    ia.nblocks = d.nblocks;
+    ia.xcd = d.order;
+    ia.trt = f->trt ? 1 : 0;
+    ia.omega = float(d.omega);
+    ia.omega64 = d.omega;
+    ia.lambda_o = float(d.lambda_o);
+    ia.lambda_o64 = d.lambda_o;
+    for (int k = 0; k < 3; ++k) {
+      ia.accel[k] = float(d.accel[k]);
+      ia.accel64[k] = d.accel[k];
+    }
+    ia.refined = 1;
+    ia.flags = d.flags;
+    ia.par = parent_cur;
+    ia.save_in = f->save[q];
+    ia.save_out = substep == 1 ? f->save[2] : f->save[q ^ 1];
+    ia.err = f->d_err;
+  }
   ops.push_back(op);
-  if (L == 0)
+  if (aa) {
+    if (substep == 2) r[L] ^= 1;
+  } else if (L == 0) {
     r[0] ^= 1;
-  else if (substep == 2)
+  } else if (substep == 2) {
     r[L] = (r[L] + 2) % 3;
+  }
 }
 
 int grid_for(const lbm_forest* f, int level, int nwork) {
@@ -285,6 +334,7 @@ int grid_for(const lbm_forest* f, int level, int nwork) {
 }
 
 hipError_t launch_level(const lbm_forest* f, const Op& op) {
+  if (op.kind == Op::kInplace) return launch_inplace(f->storage, f->n, op.ia, op.odd != 0, f->stream);
   return launch_sweep(f->storage, f->n, op.args, grid_for(f, op.level, op.args.nwork), f->lv[op.level].split,
                       f->stream);
 }
@@ -296,7 +346,7 @@ int run_ops(lbm_forest* f, const std::vector<Op>& ops, bool per_block) {
       continue;
     }
     if (op.args.nwork <= 0) continue;
-    if (!per_block) {
+    if (!per_block || op.kind == Op::kInplace) {
       HIP_TRY(launch_level(f, op));
     } else {
       const LevelDev& d = f->lv[op.level];
@@ -354,13 +404,14 @@ int check_err_flag(lbm_forest* f) {
   return LBM_OK;
 }
 
-const void* current_buffer(const lbm_forest* f, int L) { return f->lv[L].buf[f->rot[L]]; }
+const void* current_buffer(const lbm_forest* f, int L) { return f->lv[L].buf[current_index(f, L)]; }
 
 // ---- in-place streaming (lbm_set_inplace; layouts in inplace.hpp) ----------
 
 InplaceArgs inplace_args(const lbm_forest* f) {
   const LevelDev& v = f->lv[0];
-  InplaceArgs a;
+  InplaceArgs a{};  // zeroed: refined = 0, no parent, no saves (a forest of one level)
+  a.refined = 0;
   a.buf = v.buf[0];
   a.face = v.xface[0];
   a.entry = v.xface[1];  // the second x-face buffer serves as the entry buffer
@@ -383,8 +434,11 @@ InplaceArgs inplace_args(const lbm_forest* f) {
 // odd launch reads.
 int inplace_begin(lbm_forest* f) {
   if (f->layout != kLayoutNatural) return LBM_OK;
-  const LevelDev& v = f->lv[0];
+  const int L = f->inplace_level;
+  const LevelDev& v = f->lv[L];
   HIP_TRY(launch_face_copy(f->storage, f->n, v.buf[0], v.xface[0], v.nblocks, f->stream));
+  if (L > 0)  // refined: the saves of the state at the start of the coming parent step
+    HIP_TRY(launch_inplace_save_fill(f->storage, f->n, v.buf[0], f->save[f->rot[L] & 1], v.nbr, v.nblocks, f->stream));
   HIP_TRY(launch_inplace_swap(f->storage, f->n, v.buf[0], v.nblocks, f->stream));
   f->layout = kLayoutSwapped;
   return LBM_OK;
@@ -447,13 +501,15 @@ int moments_stage(int device, double** out) {
   return LBM_OK;
 }
 
-void* current_buffer_mut(lbm_forest* f, int L) { return f->lv[L].buf[f->rot[L]]; }
+void* current_buffer_mut(lbm_forest* f, int L) { return f->lv[L].buf[current_index(f, L)]; }
 
 }  // namespace
 
 int lbm::prepare_state_read(lbm_forest* f) {
   if (!f->inplace || f->layout == kLayoutNatural) return LBM_OK;
-  const LevelDev& v = f->lv[0];
+  const LevelDev& v = f->lv[f->inplace_level];
+  // a refined forest's in-place level ends every coarse step swapped
+  if (f->inplace_level > 0 && f->layout != kLayoutSwapped) return fail(LBM_E_STATE, "in-place layout out of step");
   if (f->layout == kLayoutPushed) {
     HIP_TRY(launch_inplace_entry_merge(f->storage, f->n, v.buf[0], v.xface[1], v.nblocks, f->stream));
     HIP_TRY(launch_inplace_pair_swap(f->storage, f->n, v.buf[0], v.nbr, v.nblocks, f->stream));
@@ -744,45 +800,75 @@ int lbm_init_pdfs(lbm_forest* f, const double* rho, const double* u) {
   return rc;
 }
 
+namespace {
+void release(std::vector<void*>& owner, void*& p) {
+  if (!p) return;
+  auto it = std::find(owner.begin(), owner.end(), p);
+  if (it != owner.end()) owner.erase(it);
+  (void)hipFree(p);
+  p = nullptr;
+}
+}  // namespace
+
 int lbm_set_inplace(lbm_forest* f, int on) {
   if (!f) return fail(LBM_E_INVALID, "null pointer");
   if (on != 0 && on != 1) return fail(LBM_E_INVALID, "on must be 0 or 1");
   if ((on != 0) == f->inplace) return LBM_OK;
   HIP_TRY(hipSetDevice(f->device));
-  LevelDev& v = f->lv[0];
+  const int Lf = int(f->lv.size()) - 1;  // the finest level streams in place
+  LevelDev& v = f->lv[Lf];
+  const size_t sb = storage_bytes(f->storage);
+  const size_t save_bytes = size_t(v.nblocks) * size_t(kSaveArrayCount) * size_t(f->n) * size_t(f->n) * sb;
   if (on) {
-    if (f->lv.size() != 1)
-      return fail(LBM_E_INVALID,
-                  "in-place streaming is built for forests whose leaves all lie on level 0 (this forest has %zu "
-                  "levels): level interfaces read states that an in-place update overwrites",
-                  f->lv.size());
-    // nothing queued may still use the buffer that is released
+    if (Lf > 0 && f->storage == LBM_F16_SHIFTED)
+      return fail(LBM_E_INVALID, "in-place streaming on a refined forest supports FP64 and FP32 storage");
+    if (Lf > 0 && f->interp)
+      return fail(LBM_E_STATE, "in-place streaming on a refined forest uses the homogeneous explosion");
+    // nothing queued may still use the buffers that are released
     HIP_TRY(hipStreamSynchronize(f->stream));
-    if (f->rot[0] != 0) {
-      std::swap(v.buf[0], v.buf[1]);
-      std::swap(v.xface[0], v.xface[1]);
-      f->rot[0] = 0;
+    const int c = f->rot[Lf];
+    if (c != 0) {  // the current state into buffer 0
+      std::swap(v.buf[0], v.buf[c]);
+      std::swap(v.xface[0], v.xface[c]);
     }
+    f->rot[Lf] = 0;
     f->rot_prev = f->rot;
-    // the second PDF buffer goes; its x-face buffer stays as the entry buffer
-    auto it = std::find(v.allocs.begin(), v.allocs.end(), v.buf[1]);
-    if (it != v.allocs.end()) v.allocs.erase(it);
-    if (v.buf[1]) HIP_TRY(hipFree(v.buf[1]));
-    v.buf[1] = nullptr;
+    // the other PDF buffers go; one x-face buffer stays as the entry buffer
+    for (int b = 1; b < v.nbuf; ++b) release(v.allocs, v.buf[b]);
+    for (int b = 2; b < v.nbuf; ++b) release(v.allocs, v.xface[b]);
+    if (Lf > 0) {
+      for (int q = 0; q < 3; ++q) {
+        uint8_t* p = nullptr;
+        int rc = dev_alloc(v.allocs, &p, save_bytes);
+        if (rc) return rc;
+        f->save[q] = p;
+      }
+    }
     v.nbuf = 1;
     f->inplace = true;
+    f->inplace_level = Lf;
     f->layout = kLayoutNatural;
   } else {
     int rc = prepare_state_read(f);
     if (rc) return rc;
-    const size_t sb = storage_bytes(f->storage);
-    uint8_t* p = nullptr;
-    if ((rc = dev_alloc(v.allocs, &p, size_t(v.plane) * 19 * sb))) return rc;
-    v.buf[1] = p;
-    v.nbuf = 2;
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    const int nbuf = Lf == 0 ? 2 : 3;
+    for (int b = 1; b < nbuf; ++b) {
+      uint8_t* p = nullptr;
+      if ((rc = dev_alloc(v.allocs, &p, size_t(v.plane) * 19 * sb))) return rc;
+      v.buf[b] = p;
+      if (b >= 2) {
+        if ((rc = dev_alloc(v.allocs, &p, size_t(v.nblocks) * 10 * f->n * f->n * sb))) return rc;
+        v.xface[b] = p;
+      }
+    }
+    for (int q = 0; q < 3; ++q) release(v.allocs, f->save[q]);
+    v.nbuf = nbuf;
+    f->rot[Lf] = 0;
     HIP_TRY(launch_face_copy(f->storage, f->n, v.buf[0], v.xface[0], v.nblocks, f->stream));
     HIP_TRY(hipStreamSynchronize(f->stream));
     f->inplace = false;
+    f->inplace_level = 0;
     f->rot_prev = f->rot;
   }
   invalidate_graphs(f);
@@ -807,6 +893,8 @@ int lbm_get_inplace(const lbm_forest* f, int* on) {
 
 int lbm_set_explosion_interpolation(lbm_forest* f, int on) {
   if (!f) return fail(LBM_E_INVALID, "null pointer");
+  if (on && f->inplace && f->inplace_level > 0)
+    return fail(LBM_E_STATE, "in-place streaming on a refined forest uses the homogeneous explosion");
   f->interp = on != 0;
   invalidate_graphs(f);
   return LBM_OK;
@@ -971,10 +1059,14 @@ int lbm_step_coarse(lbm_forest* f, int n_steps) {
   if (n_steps < 0) return fail(LBM_E_INVALID, "n_steps < 0");
   if (!f->omega_set) return fail(LBM_E_STATE, "lbm_set_level_omega must be called first");
   HIP_TRY(hipSetDevice(f->device));
-  if (f->inplace) {
+  if (f->inplace && f->inplace_level == 0) {
     int rc = n_steps > 0 ? inplace_begin(f) : LBM_OK;
     for (int s = 0; s < n_steps && !rc; ++s) rc = inplace_step(f);
     return rc;
+  }
+  if (f->inplace && n_steps > 0) {
+    int rc = inplace_begin(f);
+    if (rc) return rc;
   }
   for (int s = 0; s < n_steps; ++s) {
     std::vector<int> r = f->rot;
@@ -982,7 +1074,7 @@ int lbm_step_coarse(lbm_forest* f, int n_steps) {
     emit(f, 0, 1, r, nullptr, ops);
     f->rot_prev = f->rot;
     f->steps_since_state++;
-    f->post_lost = false;
+    f->post_lost = f->inplace;
     if (f->schedule == LBM_SCHED_GRAPH) {
       auto it = f->graphs.find(f->rot);
       if (it == f->graphs.end()) {
@@ -1021,7 +1113,11 @@ int lbm_time_launches(lbm_forest* f, int n_steps, double* ms, int64_t* launches,
     for (auto& e : ends) (void)hipEventDestroy(e);
   };
   auto body = [&]() -> int {
-    if (f->inplace) {
+    if (f->inplace && f->inplace_level > 0) {
+      int rc = inplace_begin(f);
+      if (rc) return rc;
+    }
+    if (f->inplace && f->inplace_level == 0) {
       // in-place streaming: the odd launch counts as substep 1, the even one as substep 2
       int rc = inplace_begin(f);
       if (rc) return rc;
@@ -1040,13 +1136,13 @@ int lbm_time_launches(lbm_forest* f, int n_steps, double* ms, int64_t* launches,
         f->post_lost = true;
       }
     }
-    for (int s = 0; s < n_steps && !f->inplace; ++s) {
+    for (int s = 0; s < n_steps && !(f->inplace && f->inplace_level == 0); ++s) {
       std::vector<int> r = f->rot;
       std::vector<Op> ops;
       emit(f, 0, 1, r, nullptr, ops);
       f->rot_prev = f->rot;
       f->steps_since_state++;
-      f->post_lost = false;
+      f->post_lost = f->inplace;
       for (const Op& op : ops) {
         const bool coal = op.kind == Op::kCoalesce;
         if (!coal && op.args.nwork <= 0) continue;
@@ -1373,7 +1469,7 @@ int lbm_set_pdfs(lbm_forest* f, const double* h) {
       f->state_set = true;
       f->layout = kLayoutNatural;
       f->post_lost = false;
-      HIP_TRY(launch_face_copy(f->storage, f->n, current_buffer(f, int(L)), v.xface[f->rot[L]], v.nblocks,
+      HIP_TRY(launch_face_copy(f->storage, f->n, current_buffer(f, int(L)), v.xface[current_index(f, int(L))], v.nblocks,
                                f->stream));
       HIP_TRY(hipStreamSynchronize(f->stream));
       return LBM_OK;

@@ -15,6 +15,7 @@
 // even launch reads for the cells at x faces.  Every buffer row is then
 // written with whole vectors.
 #include "inplace.hpp"
+#include "inplace_save.hpp"
 #include "sweep.hpp"
 
 namespace lbm {
@@ -219,14 +220,136 @@ __device__ __forceinline__ void odd_store(const InplaceArgs& a, const SlotCache&
   }
 }
 
-template <typename S, int N, int A = 0>
-__device__ __forceinline__ void odd_store_all(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0,
-                                              int j, int k, typename Form<S>::C (*h)[IGeo<S, N>::W]) {
-  odd_store<S, N, A>(a, sc, slot, cell0, i0, j, k, h);
-  if constexpr (A + 1 < 19) odd_store_all<S, N, A + 1>(a, sc, slot, cell0, i0, j, k, h);
+// ---- the finest level of a refined forest -------------------------------------
+//
+// The level's neighbour table also holds coarse codes (cells of the coarser
+// region, whose values the explosion gives, eq. ctof) besides slots and
+// walls.  The in-place launches of such a level read those values from the
+// parent level's current state (kept in two buffers) and save what the
+// back-trace and the coarser level's coalescence need (inplace_save.hpp).
+
+// Post-collision value of the level-(L-1) parent of level-L cell (lx, ly, lz)
+// of the virtual block with coarse code `code` (homogeneous explosion).
+template <typename S, int N, int A>
+__device__ __forceinline__ const S* iparent(const InplaceArgs& a, int code, int lx, int ly, int lz) {
+  constexpr int H = N / 2;
+  const int pp = kNbrCoarse0 - code;
+  const int oc = pp & 7;
+  const int px = (oc & 1 ? H : 0) + (lx >> 1), py = (oc & 2 ? H : 0) + (ly >> 1), pz = (oc & 4 ? H : 0) + (lz >> 1);
+  return static_cast<const S*>(a.par) + pdf_index<N>(A, uint32_t(pp >> 3), uint32_t(px + N * (py + N * pz)));
 }
 
-template <typename S, int N, bool TRT>
+// Odd launch (the level's first substep): the source of every cell of the
+// lane whose direction-A source is no cell of the level, from the exact
+// table entry of that source: a wall gives the bounce-back (own (x, A), or
+// the x-face copy at an x face, see odd_walls), a coarse code the exploded
+// parent value.
+template <typename S, int N, int A = 1>
+__device__ __forceinline__ void odd_specials_ref(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0,
+                                                 int j, int k, uint32_t special,
+                                                 typename Form<S>::C (*h)[IGeo<S, N>::W]) {
+  constexpr int W = IGeo<S, N>::W;
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  if ((special >> A) & 1u) {
+    const int sy = j - EY, sz = k - EZ;
+    const bool by = outside<N>(sy), bz = outside<N>(sz);
+    const S* p[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      const int sx = i0 + c - EX;
+      const int code = pick<-EX, -EY, -EZ>(sc, outside<N>(sx), by, bz);
+      const int x = i0 + c;
+      p[c] = nullptr;
+      if (code == kNbrWall) {
+        const bool xface = EX != 0 && x == (EX == 1 ? 0 : N - 1);
+        p[c] = xface ? static_cast<const S*>(a.face) + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))
+                     : static_cast<const S*>(a.buf) + pdf_index<N>(A, uint32_t(slot), uint32_t(cell0 + c));
+      } else if (code <= kNbrCoarse0) {
+        p[c] = iparent<S, N, A>(a, code, sx & (N - 1), sy & (N - 1), sz & (N - 1));
+      } else if (code < 0) {
+        atomicOr(a.err, kErrNoSource);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+      if (p[c]) h[A][c] = Form<S>::ld(p[c]);
+  }
+  if constexpr (A + 1 < 19) odd_specials_ref<S, N, A + 1>(a, sc, slot, cell0, i0, j, k, special, h);
+}
+
+// Odd-launch stores of the finest level: as odd_store, with the end cell of
+// an x-shifted row sent by its own destination (the x-diagonal block, which
+// may differ from the row's block), and every value whose destination lies
+// in the coarser region also saved (t + 1/2).
+template <typename S, int N, int A>
+__device__ __forceinline__ void odd_store_ref(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0,
+                                              int j, int k, typename Form<S>::C (*h)[IGeo<S, N>::W]) {
+  using C = typename Form<S>::C;
+  constexpr int W = IGeo<S, N>::W;
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  constexpr int END = EX == 1 ? W - 1 : 0;
+  S* __restrict__ buf = static_cast<S*>(a.buf);
+  S* __restrict__ entry = static_cast<S*>(a.entry);
+  S* __restrict__ save = static_cast<S*>(a.save_out);
+  const int dy = j + EY, dz = k + EZ;
+  const bool by = outside<N>(dy), bz = outside<N>(dz);
+  const uint32_t row = uint32_t(N * ((dy & (N - 1)) + N * (dz & (N - 1))));
+  const int nbd = pick<0, EY, EZ>(sc, false, by, bz);
+  const bool leaving_lane = EX != 0 && (EX == 1 ? i0 == N - W : i0 == 0);
+  C v[W];
+  if constexpr (EX == 1) {
+    const C prev = dpp_move<kDppRowShr1>(h[A][W - 1]);
+    v[0] = prev;
+#pragma unroll
+    for (int c = 1; c < W; ++c) v[c] = h[A][c - 1];
+  } else if constexpr (EX == -1) {
+    const C next = dpp_move<kDppRowShl1>(h[A][0]);
+#pragma unroll
+    for (int c = 0; c < W - 1; ++c) v[c] = h[A][c + 1];
+    v[W - 1] = next;
+  } else {
+#pragma unroll
+    for (int c = 0; c < W; ++c) v[c] = h[A][c];
+  }
+  if (nbd < 0) {
+    // the row's destination is no cell of the level: every cell reflects
+    // (a coarse destination's reflection slot is never read)
+    Vec<S>::store(buf + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(cell0)), h[A]);
+    if (nbd <= kNbrCoarse0) {
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        if (!(leaving_lane && c == END))
+          Form<S>::st(save + save_index<N>(uint32_t(slot), A, i0 + c, j, k), h[A][c]);
+    }
+  } else {
+    Vec<S>::store(buf + pdf_index<N>(A, uint32_t(nbd), row + uint32_t(i0)), v);
+  }
+  if constexpr (EX != 0) {
+    if (leaving_lane) {
+      const int nbx = pick<EX, EY, EZ>(sc, true, by, bz);
+      if (nbx >= 0) {
+        Form<S>::st(entry + xface_index<N, A>(uint32_t(nbx), row / N), h[A][END]);
+      } else {
+        Form<S>::st(entry + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)), h[A][END]);
+        if (nbx <= kNbrCoarse0) Form<S>::st(save + save_index<N>(uint32_t(slot), A, i0 + END, j, k), h[A][END]);
+      }
+    }
+  }
+}
+
+template <typename S, int N, bool REF, int A = 0>
+__device__ __forceinline__ void odd_store_all(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0,
+                                              int j, int k, typename Form<S>::C (*h)[IGeo<S, N>::W]) {
+  if constexpr (REF)
+    odd_store_ref<S, N, A>(a, sc, slot, cell0, i0, j, k, h);
+  else
+    odd_store<S, N, A>(a, sc, slot, cell0, i0, j, k, h);
+  if constexpr (A + 1 < 19) odd_store_all<S, N, REF, A + 1>(a, sc, slot, cell0, i0, j, k, h);
+}
+
+// REF: the finest level of a refined forest (coarse neighbours; explosion
+// and saves), else a forest of one level.
+template <typename S, int N, bool TRT, bool REF>
 __global__ void __launch_bounds__((IGeo<S, N>::T)) inplace_odd_kernel(InplaceArgs a) {
   using C = typename Form<S>::C;
   constexpr int W = IGeo<S, N>::W;
@@ -240,15 +363,74 @@ __global__ void __launch_bounds__((IGeo<S, N>::T)) inplace_odd_kernel(InplaceArg
   uint32_t wall = 0;
   odd_issue_all<S, N>(a, sc, slot, i0, j, k, h, edge, wall);
   odd_shift_all<S, N>(i0, h, edge);
-  if (wall) odd_walls<S, N>(a, sc, slot, cell0, i0, j, k, wall, h);
+  if constexpr (REF) {
+    if (wall) odd_specials_ref<S, N>(a, sc, slot, cell0, i0, j, k, wall, h);
+  } else {
+    if (wall) odd_walls<S, N>(a, sc, slot, cell0, i0, j, k, wall, h);
+  }
 #pragma unroll
   for (int c = 0; c < W; ++c) icollide<S, TRT>(a, h, c);
-  odd_store_all<S, N>(a, sc, slot, cell0, i0, j, k, h);
+  odd_store_all<S, N, REF>(a, sc, slot, cell0, i0, j, k, h);
 }
 
 // ---- even launch: pushed -> swapped -------------------------------------------
 
-template <typename S, int N, bool TRT>
+// Even launch (the level's second substep) on the finest level: a cell
+// whose direction-A source x - e_A lies in the coarser region takes what the
+// first substep streamed into that ghost cell: the level's own state at t at
+// x - 2 e_A (saved), or the exploded parent value (of the opposite direction
+// if x - 2 e_A is a wall: the ghost cell's bounce-back).
+template <typename S, int N, int A = 1>
+__device__ __forceinline__ void even_specials_ref(const InplaceArgs& a, const SlotCache& sc, int i0, int j, int k,
+                                                  typename Form<S>::C (*h)[IGeo<S, N>::W]) {
+  constexpr int W = IGeo<S, N>::W;
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  const int sy = j - EY, sz = k - EZ, zy = sy - EY, zz = sz - EZ;
+  const bool by = outside<N>(sy), bz = outside<N>(sz), bzy = outside<N>(zy), bzz = outside<N>(zz);
+  const S* p[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const int sx = i0 + c - EX, zx = sx - EX;
+    const int code = pick<-EX, -EY, -EZ>(sc, outside<N>(sx), by, bz);
+    p[c] = nullptr;
+    if (code <= kNbrCoarse0) {
+      const int cz = pick<-EX, -EY, -EZ>(sc, outside<N>(zx), bzy, bzz);
+      if (cz >= 0)
+        p[c] = static_cast<const S*>(a.save_in) +
+               save_index<N>(uint32_t(cz), A, zx & (N - 1), zy & (N - 1), zz & (N - 1));
+      else if (cz == kNbrWall)
+        p[c] = iparent<S, N, opp(A)>(a, code, sx & (N - 1), sy & (N - 1), sz & (N - 1));
+      else if (cz <= kNbrCoarse0)
+        p[c] = iparent<S, N, A>(a, cz, zx & (N - 1), zy & (N - 1), zz & (N - 1));
+      else
+        atomicOr(a.err, kErrNoSource);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < W; ++c)
+    if (p[c]) h[A][c] = Form<S>::ld(p[c]);
+  if constexpr (A + 1 < 19) even_specials_ref<S, N, A + 1>(a, sc, i0, j, k, h);
+}
+
+// Values of the finest level whose destination lies in the coarser region,
+// saved at t + 1 for the next parent step's back-trace and coalescence.
+template <typename S, int N, int A = 1>
+__device__ __forceinline__ void even_saves_ref(const InplaceArgs& a, const SlotCache& sc, int slot, int i0, int j, int k,
+                                               const typename Form<S>::C (*h)[IGeo<S, N>::W]) {
+  constexpr int W = IGeo<S, N>::W;
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  S* __restrict__ save = static_cast<S*>(a.save_out);
+  const int dy = j + EY, dz = k + EZ;
+  const bool by = outside<N>(dy), bz = outside<N>(dz);
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const int code = pick<EX, EY, EZ>(sc, outside<N>(i0 + c + EX), by, bz);
+    if (code <= kNbrCoarse0) Form<S>::st(save + save_index<N>(uint32_t(slot), A, i0 + c, j, k), h[A][c]);
+  }
+  if constexpr (A + 1 < 19) even_saves_ref<S, N, A + 1>(a, sc, slot, i0, j, k, h);
+}
+
+template <typename S, int N, bool TRT, bool REF>
 __global__ void __launch_bounds__((IGeo<S, N>::T)) inplace_even_kernel(InplaceArgs a) {
   using C = typename Form<S>::C;
   constexpr int W = IGeo<S, N>::W, N3 = N * N * N;
@@ -268,10 +450,22 @@ __global__ void __launch_bounds__((IGeo<S, N>::T)) inplace_even_kernel(InplaceAr
     if (ex(d) == -1 && i0 == N - W)
       h[d][W - 1] = Form<S>::ld(e + (uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk0);
   }
+  bool coarse_nbr = false;
+  SlotCache sc;
+  if constexpr (REF) {
+    coarse_nbr = (__builtin_amdgcn_readfirstlane(int(a.flags[slot])) & int(kHasCoarse)) != 0;
+    if (coarse_nbr) {
+      load_table(a, slot, sc);
+      even_specials_ref<S, N>(a, sc, i0, j, k, h);
+    }
+  }
 #pragma unroll
   for (int c = 0; c < W; ++c) icollide<S, TRT>(a, h, c);
 #pragma unroll
   for (int d = 0; d < 19; ++d) Vec<S>::store(p + opp(d) * N3, h[d]);
+  if constexpr (REF) {
+    if (coarse_nbr) even_saves_ref<S, N>(a, sc, slot, i0, j, k, h);
+  }
   // x-face copy for the next odd launch: the values leaving the block
   // through its x faces, by direction
   S* __restrict__ f = static_cast<S*>(a.face);
@@ -554,6 +748,24 @@ __global__ void inplace_entry_merge_kernel(S* __restrict__ buf, const S* __restr
   buf[pdf_at_rt(a, uint64_t(slot) * uint64_t(n2 * n) + uint64_t(x + n * jk), uint64_t(n2 * n))] = entry[e];
 }
 
+// Saves of the state at the start of a parent step from the natural layout:
+// every value whose destination lies in the coarser region.
+template <typename S, int N>
+__global__ void inplace_save_fill_kernel(const S* __restrict__ buf, S* __restrict__ save, const int32_t* __restrict__ nbr,
+                                         int64_t ncells) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= ncells) return;
+  constexpr int64_t N3 = int64_t(N) * N * N;
+  const int64_t slot = e / N3;
+  const int cell = int(e - slot * N3);
+  const int x = cell % N, y = (cell / N) % N, z = cell / (N * N);
+  auto side = [](int c) { return c < 0 ? -1 : (c >= N ? 1 : 0); };
+  for (int a = 1; a < 19; ++a) {
+    const int code = nbr[slot * 27 + 13 + side(x + ex(a)) + 3 * side(y + ey(a)) + 9 * side(z + ez(a))];
+    if (code <= kNbrCoarse0) save[save_index<N>(uint32_t(slot), a, x, y, z)] = buf[pdf_index<N>(a, uint64_t(slot), uint32_t(cell))];
+  }
+}
+
 template <typename S>
 int64_t inplace_grid_t(int n, int64_t nblocks) {
   switch (n) {
@@ -574,6 +786,7 @@ hipError_t launch_inplace_t(int n, const InplaceArgs& a, bool odd, hipStream_t s
     if (grid > int64_t(0x7FFFFFFF)) return hipErrorInvalidValue;
     const dim3 g = dim3(unsigned(grid)), t = dim3(unsigned(IGeo<S, N>::T));
     if constexpr (IGeo<S, N>::PACKED) {
+      if (a.refined) return hipErrorInvalidValue;  // refined forests: FP64 and FP32 storage
       if (odd) {
         if (a.trt)
           hipLaunchKernelGGL((inplace_odd_h8_kernel<N, true>), g, t, 0, stream, a);
@@ -587,16 +800,25 @@ hipError_t launch_inplace_t(int n, const InplaceArgs& a, bool odd, hipStream_t s
       }
       return hipGetLastError();
     } else {
-      if (odd) {
-        if (a.trt)
-          hipLaunchKernelGGL((inplace_odd_kernel<S, N, true>), g, t, 0, stream, a);
+      auto go2 = [&](auto trt, auto ref) {
+        constexpr bool TRT = decltype(trt)::value, REF = decltype(ref)::value;
+        if (odd)
+          hipLaunchKernelGGL((inplace_odd_kernel<S, N, TRT, REF>), g, t, 0, stream, a);
         else
-          hipLaunchKernelGGL((inplace_odd_kernel<S, N, false>), g, t, 0, stream, a);
+          hipLaunchKernelGGL((inplace_even_kernel<S, N, TRT, REF>), g, t, 0, stream, a);
+      };
+      using T0 = std::false_type;
+      using T1 = std::true_type;
+      if (a.refined) {
+        if (a.trt)
+          go2(T1{}, T1{});
+        else
+          go2(T0{}, T1{});
       } else {
         if (a.trt)
-          hipLaunchKernelGGL((inplace_even_kernel<S, N, true>), g, t, 0, stream, a);
+          go2(T1{}, T0{});
         else
-          hipLaunchKernelGGL((inplace_even_kernel<S, N, false>), g, t, 0, stream, a);
+          go2(T0{}, T0{});
       }
       return hipGetLastError();
     }
@@ -622,6 +844,8 @@ int64_t inplace_grid(int storage, int n, int64_t nblocks) {
 }
 
 hipError_t launch_inplace(int storage, int n, const InplaceArgs& a, bool odd, hipStream_t stream) {
+  if (!a.buf || !a.face || !a.entry || !a.nbr) return hipErrorInvalidValue;
+  if (a.refined && (!a.flags || !a.par || !a.save_in || !a.save_out || !a.err)) return hipErrorInvalidValue;
   switch (storage) {
     case 0: return dev::launch_inplace_t<double>(n, a, odd, stream);
     case 1: return dev::launch_inplace_t<float>(n, a, odd, stream);
@@ -652,6 +876,29 @@ hipError_t launch_inplace_swap(int storage, int n, void* buf, int64_t nblocks, h
     hipLaunchKernelGGL(dev::inplace_swap_kernel<S>, dim3(grid), dim3(kConvThreads), 0, stream, static_cast<S*>(buf),
                        ncells, n3);
     return hipGetLastError();
+  });
+}
+
+hipError_t launch_inplace_save_fill(int storage, int n, const void* buf, void* save, const int32_t* nbr, int64_t nblocks,
+                                    hipStream_t stream) {
+  const int64_t ncells = nblocks * int64_t(n) * n * n;
+  if (ncells <= 0) return hipSuccess;
+  const unsigned grid = unsigned((ncells + kConvThreads - 1) / kConvThreads);
+  return by_storage(storage, [&](auto s) -> hipError_t {
+    using S = decltype(s);
+    auto go = [&](auto nn) -> hipError_t {
+      constexpr int N = decltype(nn)::value;
+      hipLaunchKernelGGL((dev::inplace_save_fill_kernel<S, N>), dim3(grid), dim3(kConvThreads), 0, stream,
+                         static_cast<const S*>(buf), static_cast<S*>(save), nbr, ncells);
+      return hipGetLastError();
+    };
+    switch (n) {
+      case 4: return go(std::integral_constant<int, 4>{});
+      case 8: return go(std::integral_constant<int, 8>{});
+      case 16: return go(std::integral_constant<int, 16>{});
+      case 32: return go(std::integral_constant<int, 32>{});
+      default: return hipErrorInvalidValue;
+    }
   });
 }
 

@@ -32,6 +32,10 @@ namespace lbm {
 
 enum InplaceLayout : int { kLayoutNatural = 0, kLayoutSwapped = 1, kLayoutPushed = 2 };
 
+// Arrays of n^2 values per block in each save array of a refined forest's
+// in-place level (inplace_save.hpp).
+constexpr int kSaveArrayCount = 30;
+
 struct InplaceArgs {
   void* buf;             // the level's PDF buffer, block-major [slot][19][n^3]
   void* face;            // x-face copy [slot][10][n^2]: written by the even launch, read by the odd one
@@ -43,6 +47,13 @@ struct InplaceArgs {
   float omega;           // omega (SRT) or lambda_e (TRT), FP32 arithmetic forms
   float lambda_o;
   float accel[3];
+  // the finest level of a refined forest (refined != 0; see inplace_save.hpp)
+  int32_t refined;
+  const uint32_t* flags; // [slot] SlotFlags
+  const void* par;       // level-(L-1) current state (two buffers): explosion source
+  const void* save_in;   // saves of the state at the start of the parent step (second substep reads)
+  void* save_out;        // saves written: t + 1/2 (first substep), t + 1 (second substep)
+  int* err;              // error bits (table lookup failures)
   double omega64;        // the same for the FP64 form
   double lambda_o64;
   double accel64[3];
@@ -56,6 +67,11 @@ hipError_t launch_inplace(int storage, int n, const InplaceArgs& a, bool odd, hi
 
 // natural <-> swapped: per cell, (x, a) <-> (x, opp(a)).
 hipError_t launch_inplace_swap(int storage, int n, void* buf, int64_t nblocks, hipStream_t stream);
+
+// Saves of the finest level's state (natural layout) at the start of a
+// parent step (inplace_save.hpp).
+hipError_t launch_inplace_save_fill(int storage, int n, const void* buf, void* save, const int32_t* nbr, int64_t nblocks,
+                                    hipStream_t stream);
 
 // Pushed layout: the entry buffer's values back into the buffer (before
 // launch_inplace_pair_swap converts it).

@@ -8,6 +8,7 @@
 #include <type_traits>
 
 #include "forest.hpp"
+#include "inplace_save.hpp"
 #include "kernels.hpp"
 #include "lattice.hpp"
 
@@ -294,12 +295,17 @@ __device__ __forceinline__ void pair_sources(const CoalArgs& c, const int32_t* f
     use_iv[q] = false;
     if (fy >= 0) {
       const int lx = yx & (N - 1), jk = (yy & (N - 1)) + N * (yz & (N - 1));
-      p = xcopy && lx == xout ? static_cast<const S*>(c.fine1_x) + xface_index_rt<N>(A, uint32_t(fy), uint32_t(jk))
-                              : static_cast<const S*>(c.fine1) + pdf_index<N>(A, uint32_t(fy), uint32_t(lx + N * jk));
+      if (c.save_half)
+        p = static_cast<const S*>(c.save_half) + save_index<N>(uint32_t(fy), A, lx, yy & (N - 1), yz & (N - 1));
+      else
+        p = xcopy && lx == xout ? static_cast<const S*>(c.fine1_x) + xface_index_rt<N>(A, uint32_t(fy), uint32_t(jk))
+                                : static_cast<const S*>(c.fine1) + pdf_index<N>(A, uint32_t(fy), uint32_t(lx + N * jk));
     } else if (WALLS && fy == kFineWall) {
       const int wx = cx + ox + EX, wy = cy + oy + EY, wz = cz + oz + EZ;
       const int fw = fn[13 + nb_side<N>(wx) + 3 * nb_side<N>(wy) + 9 * nb_side<N>(wz)];
-      if (fw >= 0) {
+      if (fw >= 0 && c.save_t) {
+        p = static_cast<const S*>(c.save_t) + save_index<N>(uint32_t(fw), Ab, wx & (N - 1), wy & (N - 1), wz & (N - 1));
+      } else if (fw >= 0) {
         p = static_cast<const S*>(c.fine0) +
             pdf_index<N>(Ab, uint32_t(fw), uint32_t((wx & (N - 1)) + N * ((wy & (N - 1)) + N * (wz & (N - 1)))));
       } else if (INTERP) {
@@ -311,8 +317,11 @@ __device__ __forceinline__ void pair_sources(const CoalArgs& c, const int32_t* f
       }
     } else if (fz >= 0) {
       const int lx = zx & (N - 1), jk = (zy & (N - 1)) + N * (zz & (N - 1));
-      p = xcopy && lx == xout ? static_cast<const S*>(c.fine0_x) + xface_index_rt<N>(A, uint32_t(fz), uint32_t(jk))
-                              : static_cast<const S*>(c.fine0) + pdf_index<N>(A, uint32_t(fz), uint32_t(lx + N * jk));
+      if (c.save_t)
+        p = static_cast<const S*>(c.save_t) + save_index<N>(uint32_t(fz), A, lx, zy & (N - 1), zz & (N - 1));
+      else
+        p = xcopy && lx == xout ? static_cast<const S*>(c.fine0_x) + xface_index_rt<N>(A, uint32_t(fz), uint32_t(jk))
+                                : static_cast<const S*>(c.fine0) + pdf_index<N>(A, uint32_t(fz), uint32_t(lx + N * jk));
     } else if (WALLS && fz == kFineWall) {
       if (INTERP) {
         iv[q] = interp_value<S, N>(static_cast<const S*>(c.cur), nbs, i + half_floor(ox - EX), j + half_floor(oy - EY),

@@ -85,6 +85,10 @@ struct CoalArgs {
   int* err;                   // error bits (table lookup failures)
   int32_t interp;             // 1: interpolated explosion of the coarse values the children trace back to
   int32_t walls;              // 1: the forest has a non-periodic axis (no-slip walls)
+  // finer level streamed in place (non-null): its values at t and t + 1/2 come
+  // from its save arrays instead of fine0 / fine1 (see inplace_save.hpp)
+  const void* save_t;         // saves of the finer state at the start of its parent step
+  const void* save_half;      // saves of the finer state after its first substep
 };
 
 hipError_t launch_coalesce(int storage, int n, const CoalArgs& a, hipStream_t stream);

@@ -8,6 +8,7 @@
 
 #include "../../include/lbm_refined.h"
 #include "forest.hpp"
+#include "inplace.hpp"
 #include "kernels.hpp"
 
 namespace lbm {
@@ -45,11 +46,13 @@ struct LevelDev {
 // One launch of the coarse step: a level substep's sweep, or the
 // coalescence that precedes it on a level with finer neighbours.
 struct Op {
-  enum Kind { kSweep = 0, kCoalesce = 1 };
+  enum Kind { kSweep = 0, kCoalesce = 1, kInplace = 2 };
   int level;
   int kind = kSweep;
   SweepArgs args;
   CoalArgs coal;
+  InplaceArgs ia;   // kInplace: a launch of the in-place finest level
+  int odd = 0;      // kInplace: 1 the odd launch (first substep), 0 the even one
 };
 
 }  // namespace lbm
@@ -86,6 +89,8 @@ struct lbm_forest {
   bool inplace = false;                     // in-place streaming (lbm_set_inplace): level 0 keeps one buffer
   int layout = 0;                           // its layout (InplaceLayout in inplace.hpp)
   bool post_lost = false;                   // in-place steps left no state of the last step's start (regrid needs it)
+  int inplace_level = 0;                    // the level streamed in place (the finest; 0 on a one-level forest)
+  void* save[3] = {nullptr, nullptr, nullptr};  // refined in place: saves at t (two, by parent-step parity), t + 1/2
   unsigned long long* d_check = nullptr;    // its figures (see CoalArgs::check)
   double* d_partials = nullptr;
   std::vector<void*> allocations;
@@ -103,7 +108,13 @@ struct lbm_forest {
 
 namespace lbm {
 
-inline const void* current_state(const lbm_forest* f, int L) { return f->lv[L].buf[f->rot[L]]; }
+// Buffer holding level L's current state: the rotating index, or buffer 0
+// for the level streamed in place (whose rotation entry is then the parity
+// of its parent steps).
+inline int current_index(const lbm_forest* f, int L) {
+  return f->inplace && L == f->inplace_level ? 0 : f->rot[L];
+}
+inline const void* current_state(const lbm_forest* f, int L) { return f->lv[L].buf[current_index(f, L)]; }
 
 // Sets the thread's error message and returns `code`.
 int set_error(int code, const char* fmt, ...);

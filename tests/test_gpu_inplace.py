@@ -2,8 +2,9 @@
 (lbm_set_inplace).
 
 Section 4.1 keeps two grids and names the AA pattern as the in-place
-alternative; the library builds it for forests whose leaves all lie on
-level 0.  Its results must equal the two-buffer path's bitwise, for every
+alternative.  This file covers forests whose leaves all lie on level 0
+(test_gpu_inplace_refined.py the finest level of refined forests).  Results
+must equal the two-buffer path's bitwise, for every
 storage form, SRT and TRT with a body force, periodic axes and no-slip walls
 (section 2.2), whatever layout the buffer holds when a query reads it (odd
 and even step counts); FP64 storage must meet the FP64 oracle to rounding
@@ -180,8 +181,8 @@ def test_memory_footprint_halves():
 
 
 def test_refusals():
-    two = lbm.Forest((2, 2, 2), 4, 1, refine=lambda L, x, y, z: (x, y, z) == (0, 0, 0), storage="f32")
-    with pytest.raises(lbm.LBMError) as e:
+    two = lbm.Forest((2, 2, 2), 8, 1, refine=lambda L, x, y, z: (x, y, z) == (0, 0, 0), storage="f16")
+    with pytest.raises(lbm.LBMError) as e:  # refined forests: FP64 and FP32 storage
         two.set_inplace(True)
     assert e.value.name == "LBM_E_INVALID"
     two.close()
