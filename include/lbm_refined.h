@@ -217,30 +217,37 @@ int lbm_mass(lbm_forest *f, double *mass, double momentum[3]);
  * average to its values, so mass and momentum are kept, and zero slopes give
  * eq. ctof.  It applies to every exploded value the sweeps and the
  * coalescence read; lbm_regrid still explodes whole new blocks
- * homogeneously.  Invalidates captured graphs. */
+ * homogeneously.  Invalidates captured graphs.  LBM_E_STATE for on != 0
+ * while a refined forest streams in place. */
 int lbm_set_explosion_interpolation(lbm_forest *f, int on);
 
 /* In-place streaming (on != 0; off by default).  Section 4.1 stores two
  * grids, source and destination, and names the AA pattern as the in-place
- * alternative that refinement does not readily admit.  The library builds
- * it for forests whose leaves all lie on level 0 (no level interfaces):
- * level 0 keeps one PDF buffer instead of two, which halves the device
- * memory of the PDFs (the second buffer's x-face copy stays, 1.6 % of a
- * buffer at n = 32, to hold the values that cross x faces); the bytes moved
- * per cell update stay 38 s (19 values read and 19 written).  Coarse steps alternate an
- * odd launch (pull from the neighbours, collide, push to them) and an even
- * one (collide in place); the buffer holds the post-collision state in a
- * layout that alternates with them and is brought back to the natural
- * layout, in place, before lbm_get_moments, lbm_get_moments_static,
- * lbm_mass, lbm_get_pdfs or the indicator calls read it.  Results equal
- * those of two-buffer streaming bitwise, SRT and TRT with a body force,
- * periodic axes and no-slip walls alike.  on = 1 frees the second buffer
- * (after synchronizing the stream); on = 0 allocates it again.  While on,
- * lbm_autotune and lbm_regrid return LBM_E_STATE, and lbm_regrid also does
- * until a coarse step with two-buffer streaming has been taken (it needs
- * the state at the start of the last coarse step).  Invalidates captured
- * graphs.  Errors: LBM_E_INVALID (on not 0 or 1; on = 1 on a forest with
- * more than one level), LBM_E_OOM (on = 0), LBM_E_HIP. */
+ * alternative that refinement does not readily admit.  The library streams
+ * the finest level in place: it keeps one PDF buffer instead of two (a
+ * forest of one level) or three (the finest level of a refined forest);
+ * the bytes moved per cell update stay 38 s (19 values read and 19
+ * written).  The finest level's steps alternate an odd launch (pull from
+ * the neighbours, collide, push to them) and an even one (collide in
+ * place); on a refined forest they are its first and second substeps, the
+ * explosion reads the parent level's current state, and the values the
+ * finest cells send into the fine ghost layers (section 4) at t and t + 1/2
+ * are saved for the second substep's back-trace and the coarser level's
+ * coalescence (30 n^2 values per block, three arrays).  The buffer holds the
+ * post-collision state in a layout that alternates with the launches and is
+ * brought back to the natural layout, in place, before lbm_get_moments,
+ * lbm_get_moments_static, lbm_mass, lbm_get_pdfs or the indicator calls
+ * read it.  Results equal those of two-buffer streaming bitwise, SRT and
+ * TRT with a body force, periodic axes and no-slip walls alike.  on = 1
+ * frees the finest level's other buffers (after synchronizing the stream;
+ * one x-face buffer stays, to hold the values that cross x faces); on = 0
+ * allocates them again.  While on, lbm_autotune and lbm_regrid return
+ * LBM_E_STATE, and lbm_regrid also does until a coarse step with
+ * two-buffer streaming has been taken (it needs the state at the start of
+ * the last coarse step).  Invalidates captured graphs.  Errors:
+ * LBM_E_INVALID (on not 0 or 1; on = 1 on a refined forest with FP16
+ * storage), LBM_E_STATE (on = 1 on a refined forest with the interpolated
+ * explosion, which then stays off), LBM_E_OOM, LBM_E_HIP. */
 int lbm_set_inplace(lbm_forest *f, int on);
 
 /* Whether in-place streaming is on (*on = 1) or off (0). */
