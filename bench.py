@@ -375,7 +375,7 @@ def main():
                                          "ms_per_step": round(msp, 3)}
         gp.close()
         del gp
-        for storage in ("f64", "f32"):
+        for storage in ("f64", "f32", "f16"):
             forms[f"{storage}_inplace_finest_graph"] = inplace_refined_form(torch, lbm, W, w, stream, storage, 5)
             print(f"{storage} finest level in place: {forms[storage + '_inplace_finest_graph']['MLUPS']} MLUPS",
                   file=sys.stderr, flush=True)

@@ -245,9 +245,9 @@ int lbm_set_explosion_interpolation(lbm_forest *f, int on);
  * LBM_E_STATE, and lbm_regrid also does until a coarse step with
  * two-buffer streaming has been taken (it needs the state at the start of
  * the last coarse step).  Invalidates captured graphs.  Errors:
- * LBM_E_INVALID (on not 0 or 1; on = 1 on a refined forest with FP16
- * storage), LBM_E_STATE (on = 1 on a refined forest with the interpolated
- * explosion, which then stays off), LBM_E_OOM, LBM_E_HIP. */
+ * LBM_E_INVALID (on not 0 or 1), LBM_E_STATE (on = 1 on a refined forest
+ * with the interpolated explosion, which then stays off), LBM_E_OOM,
+ * LBM_E_HIP. */
 int lbm_set_inplace(lbm_forest *f, int on);
 
 /* Whether in-place streaming is on (*on = 1) or off (0). */

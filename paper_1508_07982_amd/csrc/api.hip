@@ -820,8 +820,6 @@ int lbm_set_inplace(lbm_forest* f, int on) {
   const size_t sb = storage_bytes(f->storage);
   const size_t save_bytes = size_t(v.nblocks) * size_t(kSaveArrayCount) * size_t(f->n) * size_t(f->n) * sb;
   if (on) {
-    if (Lf > 0 && f->storage == LBM_F16_SHIFTED)
-      return fail(LBM_E_INVALID, "in-place streaming on a refined forest supports FP64 and FP32 storage");
     if (Lf > 0 && f->interp)
       return fail(LBM_E_STATE, "in-place streaming on a refined forest uses the homogeneous explosion");
     // nothing queued may still use the buffers that are released

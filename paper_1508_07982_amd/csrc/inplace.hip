@@ -645,7 +645,147 @@ __device__ __forceinline__ void odd_store_all_h8(const InplaceArgs& a, const Slo
   if constexpr (A + 1 < 19) odd_store_all_h8<N, A + 1>(a, sc, slot, cell0, i0, j, k, q);
 }
 
-template <int N, bool TRT>
+// ---- packed FP16 on the finest level of a refined forest (as the REF paths above)
+
+__device__ __forceinline__ void put_half(uint32_t* q, int c, uint16_t v) {
+  uint32_t& w = q[c >> 1];
+  w = c & 1 ? ((w & 0xFFFFu) | (uint32_t(v) << 16)) : ((w & 0xFFFF0000u) | uint32_t(v));
+}
+__device__ __forceinline__ uint16_t get_half(const uint32_t* q, int c) {
+  return uint16_t(c & 1 ? q[c >> 1] >> 16 : q[c >> 1] & 0xFFFFu);
+}
+
+template <int N, int A = 1>
+__device__ __forceinline__ void odd_specials_ref_h8(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0,
+                                                    int j, int k, uint32_t special, uint32_t (*q)[4]) {
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  if ((special >> A) & 1u) {
+    const int sy = j - EY, sz = k - EZ;
+    const bool by = outside<N>(sy), bz = outside<N>(sz);
+    const uint16_t* p[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int sx = i0 + c - EX;
+      const int code = pick<-EX, -EY, -EZ>(sc, outside<N>(sx), by, bz);
+      const int x = i0 + c;
+      p[c] = nullptr;
+      if (code == kNbrWall) {
+        const bool xface = EX != 0 && x == (EX == 1 ? 0 : N - 1);
+        p[c] = xface ? static_cast<const uint16_t*>(a.face) + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))
+                     : static_cast<const uint16_t*>(a.buf) + pdf_index<N>(A, uint32_t(slot), uint32_t(cell0 + c));
+      } else if (code <= kNbrCoarse0) {
+        p[c] = reinterpret_cast<const uint16_t*>(iparent<__half, N, A>(a, code, sx & (N - 1), sy & (N - 1), sz & (N - 1)));
+      } else if (code < 0) {
+        atomicOr(a.err, kErrNoSource);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (p[c]) put_half(q[A], c, *p[c]);
+  }
+  if constexpr (A + 1 < 19) odd_specials_ref_h8<N, A + 1>(a, sc, slot, cell0, i0, j, k, special, q);
+}
+
+template <int N, int A>
+__device__ __forceinline__ void odd_store_ref_h8(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0,
+                                                 int j, int k, uint32_t (*q)[4]) {
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  constexpr int END = EX == 1 ? 7 : 0;
+  uint16_t* __restrict__ buf = static_cast<uint16_t*>(a.buf);
+  uint16_t* __restrict__ entry = static_cast<uint16_t*>(a.entry);
+  uint16_t* __restrict__ save = static_cast<uint16_t*>(a.save_out);
+  const int dy = j + EY, dz = k + EZ;
+  const bool by = outside<N>(dy), bz = outside<N>(dz);
+  const uint32_t row = uint32_t(N * ((dy & (N - 1)) + N * (dz & (N - 1))));
+  const int nbd = pick<0, EY, EZ>(sc, false, by, bz);
+  const bool leaving_lane = EX != 0 && (EX == 1 ? i0 == N - 8 : i0 == 0);
+  uint32_t o[4] = {q[A][0], q[A][1], q[A][2], q[A][3]};
+  if constexpr (EX == 1) {
+    shift_h8<1>(q[A], dpp_move_u32<kDppRowShr1>(q[A][3]), o);
+  } else if constexpr (EX == -1) {
+    shift_h8<-1>(q[A], dpp_move_u32<kDppRowShl1>(q[A][0]), o);
+  }
+  if (nbd < 0) {
+    store_u32x4(buf + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(cell0)), q[A]);
+    if (nbd <= kNbrCoarse0) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (!(leaving_lane && c == END)) save[save_index<N>(uint32_t(slot), A, i0 + c, j, k)] = get_half(q[A], c);
+    }
+  } else {
+    store_u32x4(buf + pdf_index<N>(A, uint32_t(nbd), row + uint32_t(i0)), o);
+  }
+  if constexpr (EX != 0) {
+    if (leaving_lane) {
+      const uint16_t end = get_half(q[A], END);
+      const int nbx = pick<EX, EY, EZ>(sc, true, by, bz);
+      if (nbx >= 0) {
+        entry[xface_index<N, A>(uint32_t(nbx), row / N)] = end;
+      } else {
+        entry[xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))] = end;
+        if (nbx <= kNbrCoarse0) save[save_index<N>(uint32_t(slot), A, i0 + END, j, k)] = end;
+      }
+    }
+  }
+}
+
+template <int N, bool REF, int A = 0>
+__device__ __forceinline__ void odd_store_sel_h8(const InplaceArgs& a, const SlotCache& sc, int slot, int cell0, int i0,
+                                                 int j, int k, uint32_t (*q)[4]) {
+  if constexpr (REF)
+    odd_store_ref_h8<N, A>(a, sc, slot, cell0, i0, j, k, q);
+  else
+    odd_store_h8<N, A>(a, sc, slot, cell0, i0, j, k, q);
+  if constexpr (A + 1 < 19) odd_store_sel_h8<N, REF, A + 1>(a, sc, slot, cell0, i0, j, k, q);
+}
+
+template <int N, int A = 1>
+__device__ __forceinline__ void even_specials_ref_h8(const InplaceArgs& a, const SlotCache& sc, int i0, int j, int k,
+                                                     uint32_t (*q)[4]) {
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  const int sy = j - EY, sz = k - EZ, zy = sy - EY, zz = sz - EZ;
+  const bool by = outside<N>(sy), bz = outside<N>(sz), bzy = outside<N>(zy), bzz = outside<N>(zz);
+  const uint16_t* p[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int sx = i0 + c - EX, zx = sx - EX;
+    const int code = pick<-EX, -EY, -EZ>(sc, outside<N>(sx), by, bz);
+    p[c] = nullptr;
+    if (code <= kNbrCoarse0) {
+      const int cz = pick<-EX, -EY, -EZ>(sc, outside<N>(zx), bzy, bzz);
+      if (cz >= 0)
+        p[c] = static_cast<const uint16_t*>(a.save_in) +
+               save_index<N>(uint32_t(cz), A, zx & (N - 1), zy & (N - 1), zz & (N - 1));
+      else if (cz == kNbrWall)
+        p[c] = reinterpret_cast<const uint16_t*>(iparent<__half, N, opp(A)>(a, code, sx & (N - 1), sy & (N - 1), sz & (N - 1)));
+      else if (cz <= kNbrCoarse0)
+        p[c] = reinterpret_cast<const uint16_t*>(iparent<__half, N, A>(a, cz, zx & (N - 1), zy & (N - 1), zz & (N - 1)));
+      else
+        atomicOr(a.err, kErrNoSource);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    if (p[c]) put_half(q[A], c, *p[c]);
+  if constexpr (A + 1 < 19) even_specials_ref_h8<N, A + 1>(a, sc, i0, j, k, q);
+}
+
+template <int N, int A = 1>
+__device__ __forceinline__ void even_saves_ref_h8(const InplaceArgs& a, const SlotCache& sc, int slot, int i0, int j,
+                                                  int k, const uint32_t (*q)[4]) {
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  uint16_t* __restrict__ save = static_cast<uint16_t*>(a.save_out);
+  const int dy = j + EY, dz = k + EZ;
+  const bool by = outside<N>(dy), bz = outside<N>(dz);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int code = pick<EX, EY, EZ>(sc, outside<N>(i0 + c + EX), by, bz);
+    if (code <= kNbrCoarse0) save[save_index<N>(uint32_t(slot), A, i0 + c, j, k)] = get_half(q[A], c);
+  }
+  if constexpr (A + 1 < 19) even_saves_ref_h8<N, A + 1>(a, sc, slot, i0, j, k, q);
+}
+
+template <int N, bool TRT, bool REF>
 __global__ void __launch_bounds__((IGeo<__half, N>::T)) inplace_odd_h8_kernel(InplaceArgs a) {
   int slot, cell0;
   tile_of<__half, N>(a, slot, cell0);
@@ -657,12 +797,16 @@ __global__ void __launch_bounds__((IGeo<__half, N>::T)) inplace_odd_h8_kernel(In
   uint32_t wall = 0;
   odd_issue_all_h8<N>(a, sc, slot, i0, j, k, q, edge, wall);
   odd_shift_all_h8<N>(i0, q, edge);
-  if (wall) odd_walls_h8<N>(a, sc, slot, cell0, i0, j, k, wall, q);
+  if constexpr (REF) {
+    if (wall) odd_specials_ref_h8<N>(a, sc, slot, cell0, i0, j, k, wall, q);
+  } else {
+    if (wall) odd_walls_h8<N>(a, sc, slot, cell0, i0, j, k, wall, q);
+  }
   collide_h8<TRT>(a, q);
-  odd_store_all_h8<N>(a, sc, slot, cell0, i0, j, k, q);
+  odd_store_sel_h8<N, REF>(a, sc, slot, cell0, i0, j, k, q);
 }
 
-template <int N, bool TRT>
+template <int N, bool TRT, bool REF>
 __global__ void __launch_bounds__((IGeo<__half, N>::T)) inplace_even_h8_kernel(InplaceArgs a) {
   constexpr int N3 = N * N * N;
   int slot, cell0;
@@ -684,9 +828,21 @@ __global__ void __launch_bounds__((IGeo<__half, N>::T)) inplace_even_h8_kernel(I
     if (ex(d) == -1 && i0 == N - 8)
       q[d][3] = (q[d][3] & 0xFFFFu) | (uint32_t(e[(uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk0]) << 16);
   }
+  bool coarse_nbr = false;
+  SlotCache sc;
+  if constexpr (REF) {
+    coarse_nbr = (__builtin_amdgcn_readfirstlane(int(a.flags[slot])) & int(kHasCoarse)) != 0;
+    if (coarse_nbr) {
+      load_table(a, slot, sc);
+      even_specials_ref_h8<N>(a, sc, i0, j, k, q);
+    }
+  }
   collide_h8<TRT>(a, q);
 #pragma unroll
   for (int d = 0; d < 19; ++d) store_u32x4(p + opp(d) * N3, q[d]);
+  if constexpr (REF) {
+    if (coarse_nbr) even_saves_ref_h8<N>(a, sc, slot, i0, j, k, q);
+  }
   uint16_t* __restrict__ f = static_cast<uint16_t*>(a.face);
   const uint32_t jk = uint32_t(j + N * k);
 #pragma unroll
@@ -786,17 +942,25 @@ hipError_t launch_inplace_t(int n, const InplaceArgs& a, bool odd, hipStream_t s
     if (grid > int64_t(0x7FFFFFFF)) return hipErrorInvalidValue;
     const dim3 g = dim3(unsigned(grid)), t = dim3(unsigned(IGeo<S, N>::T));
     if constexpr (IGeo<S, N>::PACKED) {
-      if (a.refined) return hipErrorInvalidValue;  // refined forests: FP64 and FP32 storage
-      if (odd) {
-        if (a.trt)
-          hipLaunchKernelGGL((inplace_odd_h8_kernel<N, true>), g, t, 0, stream, a);
+      auto go8 = [&](auto trt, auto ref) {
+        constexpr bool TRT = decltype(trt)::value, REF = decltype(ref)::value;
+        if (odd)
+          hipLaunchKernelGGL((inplace_odd_h8_kernel<N, TRT, REF>), g, t, 0, stream, a);
         else
-          hipLaunchKernelGGL((inplace_odd_h8_kernel<N, false>), g, t, 0, stream, a);
+          hipLaunchKernelGGL((inplace_even_h8_kernel<N, TRT, REF>), g, t, 0, stream, a);
+      };
+      using F0 = std::false_type;
+      using F1 = std::true_type;
+      if (a.refined) {
+        if (a.trt)
+          go8(F1{}, F1{});
+        else
+          go8(F0{}, F1{});
       } else {
         if (a.trt)
-          hipLaunchKernelGGL((inplace_even_h8_kernel<N, true>), g, t, 0, stream, a);
+          go8(F1{}, F0{});
         else
-          hipLaunchKernelGGL((inplace_even_h8_kernel<N, false>), g, t, 0, stream, a);
+          go8(F0{}, F0{});
       }
       return hipGetLastError();
     } else {

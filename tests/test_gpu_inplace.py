@@ -181,11 +181,6 @@ def test_memory_footprint_halves():
 
 
 def test_refusals():
-    two = lbm.Forest((2, 2, 2), 8, 1, refine=lambda L, x, y, z: (x, y, z) == (0, 0, 0), storage="f16")
-    with pytest.raises(lbm.LBMError) as e:  # refined forests: FP64 and FP32 storage
-        two.set_inplace(True)
-    assert e.value.name == "LBM_E_INVALID"
-    two.close()
     g = make("periodic4", "f32", True)
     g.step_coarse(1)
     with pytest.raises(lbm.LBMError) as e:

@@ -7,7 +7,7 @@ into the fine ghost layers at t and t + 1/2, section 4) are saved by the
 in-place launches, and the explosion reads the parent level's current state
 (eq. ctof).  Results must equal the two-buffer path's bitwise on two- and
 three-level forests, with walls (section 2.2) and TRT with a body force, in
-FP64 and FP32 storage; FP64 meets the oracle to rounding order; the finest
+every storage form; FP64 meets the oracle to rounding order; the finest
 level's memory shrinks by two buffers less the saves.
 """
 
@@ -89,17 +89,18 @@ def run_pair(name, storage, chunks, trt=None, schedule="graph"):
     b.close()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("name", sorted(SPECS))
 def test_refined_inplace_equals_two_buffer_bitwise(name, storage):
     say(f"refined in place vs two-buffer {name} {storage}")
     run_pair(name, storage, [1, 1, 2, 3])
 
 
+@pytest.mark.parametrize("storage", ["f64", "f16"])
 @pytest.mark.parametrize("name", ["three8", "corner_box8"])
-def test_refined_inplace_trt_force_bitwise(name):
-    say(f"refined in place TRT + force {name}")
-    run_pair(name, "f64", [2, 3], trt=TRT)
+def test_refined_inplace_trt_force_bitwise(name, storage):
+    say(f"refined in place TRT + force {name} {storage}")
+    run_pair(name, storage, [2, 3], trt=TRT)
 
 
 def test_refined_inplace_direct_schedule_bitwise():
