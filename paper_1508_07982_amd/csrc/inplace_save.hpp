@@ -27,18 +27,39 @@ namespace dev {
 constexpr int kSaveArrays = kSaveArrayCount;
 
 __host__ __device__ constexpr int save_count(int a) { return (ex(a) != 0) + (ey(a) != 0) + (ez(a) != 0); }
-__host__ __device__ constexpr int save_base(int a) {
+// First array of direction a: directions 1 .. 6 lie along one axis, 7 .. 18
+// along two (closed form, checked against the sum below), so that a
+// direction known only at run time costs no loop.
+__host__ __device__ constexpr int save_base(int a) { return a <= 6 ? a - 1 : 6 + 2 * (a - 7); }
+constexpr bool save_base_matches() {
   int b = 0;
-  for (int d = 1; d < a; ++d) b += save_count(d);
-  return b;
+  for (int d = 1; d < 19; ++d) {
+    if (save_base(d) != b) return false;
+    b += save_count(d);
+  }
+  return b == kSaveArrays;
 }
-static_assert(save_base(19) == kSaveArrays, "30 save arrays per slot");
+static_assert(save_base_matches(), "30 save arrays per slot, axis directions first");
+
+// Components of direction a from packed tables (2 bits per direction,
+// component + 1): cheap for a direction known only at run time.
+__host__ __device__ constexpr uint64_t pack_components(int axis) {
+  uint64_t t = 0;
+  for (int a = 0; a < 19; ++a)
+    t |= uint64_t((axis == 0 ? ex(a) : axis == 1 ? ey(a) : ez(a)) + 1) << (2 * a);
+  return t;
+}
+template <int AXIS>
+__host__ __device__ __forceinline__ int comp_rt(int a) {
+  constexpr uint64_t t = pack_components(AXIS);
+  return int((t >> (2 * a)) & 3u) - 1;
+}
 
 // Index of the value of cell (i, j, k) of block `slot` in direction a, for a
 // cell whose neighbour (i, j, k) + e_a lies outside the block.
 template <int N>
 __device__ __forceinline__ uint64_t save_index(uint32_t slot, int a, int i, int j, int k) {
-  const int e[3] = {ex(a), ey(a), ez(a)};
+  const int e[3] = {comp_rt<0>(a), comp_rt<1>(a), comp_rt<2>(a)};
   const int c[3] = {i, j, k};
   int rank = 0, axis = -1;
 #pragma unroll
