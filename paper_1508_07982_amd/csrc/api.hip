@@ -822,6 +822,19 @@ int lbm_set_inplace(lbm_forest* f, int on) {
   if (on) {
     if (Lf > 0 && f->interp)
       return fail(LBM_E_STATE, "in-place streaming on a refined forest uses the homogeneous explosion");
+    // the saves first, so that a failed allocation leaves the forest as it was
+    void* saves[3] = {nullptr, nullptr, nullptr};
+    if (Lf > 0) {
+      for (int q = 0; q < 3; ++q) {
+        uint8_t* p = nullptr;
+        int rc = dev_alloc(v.allocs, &p, save_bytes);
+        if (rc) {
+          for (void*& r : saves) release(v.allocs, r);
+          return rc;
+        }
+        saves[q] = p;
+      }
+    }
     // nothing queued may still use the buffers that are released
     HIP_TRY(hipStreamSynchronize(f->stream));
     const int c = f->rot[Lf];
@@ -834,14 +847,7 @@ int lbm_set_inplace(lbm_forest* f, int on) {
     // the other PDF buffers go; one x-face buffer stays as the entry buffer
     for (int b = 1; b < v.nbuf; ++b) release(v.allocs, v.buf[b]);
     for (int b = 2; b < v.nbuf; ++b) release(v.allocs, v.xface[b]);
-    if (Lf > 0) {
-      for (int q = 0; q < 3; ++q) {
-        uint8_t* p = nullptr;
-        int rc = dev_alloc(v.allocs, &p, save_bytes);
-        if (rc) return rc;
-        f->save[q] = p;
-      }
-    }
+    for (int q = 0; q < 3; ++q) f->save[q] = saves[q];
     v.nbuf = 1;
     f->inplace = true;
     f->inplace_level = Lf;
@@ -851,14 +857,28 @@ int lbm_set_inplace(lbm_forest* f, int on) {
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(f->stream));
     const int nbuf = Lf == 0 ? 2 : 3;
-    for (int b = 1; b < nbuf; ++b) {
+    // the buffers first, into temporaries: a failed allocation leaves in-place streaming on
+    void* bufs[3] = {nullptr, nullptr, nullptr};
+    void* faces[3] = {nullptr, nullptr, nullptr};
+    for (int b = 1; b < nbuf && !rc; ++b) {
       uint8_t* p = nullptr;
-      if ((rc = dev_alloc(v.allocs, &p, size_t(v.plane) * 19 * sb))) return rc;
-      v.buf[b] = p;
+      if ((rc = dev_alloc(v.allocs, &p, size_t(v.plane) * 19 * sb))) break;
+      bufs[b] = p;
       if (b >= 2) {
-        if ((rc = dev_alloc(v.allocs, &p, size_t(v.nblocks) * 10 * f->n * f->n * sb))) return rc;
-        v.xface[b] = p;
+        if ((rc = dev_alloc(v.allocs, &p, size_t(v.nblocks) * 10 * f->n * f->n * sb))) break;
+        faces[b] = p;
       }
+    }
+    if (rc) {
+      for (int b = 0; b < 3; ++b) {
+        release(v.allocs, bufs[b]);
+        release(v.allocs, faces[b]);
+      }
+      return rc;
+    }
+    for (int b = 1; b < nbuf; ++b) {
+      v.buf[b] = bufs[b];
+      if (b >= 2) v.xface[b] = faces[b];
     }
     for (int q = 0; q < 3; ++q) release(v.allocs, f->save[q]);
     v.nbuf = nbuf;
