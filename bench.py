@@ -104,7 +104,7 @@ def level_table(g, sweeps, s_bytes, coal=None):
 def launch_table(res):
     """Autotuner choice per level: [persistent workgroups per CU (0: one
     per work unit), tile order (1: grouped by XCD), workgroups per tile]."""
-    return {f"L{r['level']}": [r["persistent"], r["order"], r["split"]] for r in res}
+    return {f"L{r['level']}": [r["persistent"], r["order"], r["split"], r["fuse"]] for r in res}
 
 
 def roofline_block(g, storage, sweeps):

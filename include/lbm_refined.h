@@ -273,6 +273,26 @@ int lbm_set_coalescence_check(lbm_forest *f, int on);
  * Synchronizes the stream. */
 int lbm_coalescence_check(lbm_forest *f, double out[3]);
 
+/* Where the coalescence of level L (eq. ftoc) runs (Algorithm 1 places it
+ * after level L+1's two substeps and before level L's next stream).  With
+ * fusion on for level L+1: inside the launch of level L+1's second substep,
+ * whose workgroups it shares, when that launch has one workgroup per work
+ * tile and the homogeneous explosion; its inputs (level L+1's states at t
+ * and t + 1/2, level L's current state) are ones that substep does not
+ * write.  Otherwise, and on the per-block schedule, with a persistent grid
+ * on level L+1, the interpolated explosion or an in-place level L+1: a launch
+ * of its own before level L's sweep.  Results are bitwise the same either
+ * way.  lbm_set_coalescence_fusion sets every level (on = 1, the default, or
+ * 0; also for levels a regrid creates); lbm_set_level_fusion sets one level
+ * (on = 1, 0, or -1 for the forest-wide setting; kept across lbm_regrid for
+ * levels that still exist), and the autotuner picks it per level;
+ * lbm_get_level_fusion gives the setting in force (1 or 0).  Invalidate
+ * captured graphs.  Errors: LBM_E_INVALID (null pointer, level out of range,
+ * on out of range). */
+int lbm_set_coalescence_fusion(lbm_forest *f, int on);
+int lbm_set_level_fusion(lbm_forest *f, int level, int on);
+int lbm_get_level_fusion(const lbm_forest *f, int level, int *on);
+
 /* Schedule of lbm_step_coarse: LBM_SCHED_GRAPH (default), _DIRECT or
  * _PER_BLOCK.  All three give bitwise identical results. */
 int lbm_set_schedule(lbm_forest *f, int schedule);
@@ -300,14 +320,17 @@ int lbm_get_level_launch(const lbm_forest *f, int level, int *persistent, int *o
  * one launch per substep, the step captured as a graph).  Times each
  * candidate (persistent, order, split) -- one workgroup per work unit with
  * order {0, 1} x split {1, 2, 4}, and persistent grids of {1, 2, 4, 8}
- * workgroups per CU with order {0, 1} -- with lbm_time_sweeps over one
- * warm-up and n_steps >= 1 coarse steps, in two passes over all candidates
- * (each candidate keeps its faster pass), keeps for every level the
- * candidate with the smallest mean step time of that level, and applies it.
- * With TRT (lbm_set_trt_force) a persistent candidate runs one workgroup
- * per work unit.
- * result[4 * L + {0, 1, 2, 3}] = chosen persistent, order, split and that
- * level's mean time per level step in ms.  The PDF state is saved before
+ * workgroups per CU with order {0, 1} -- each with the coarser level's
+ * coalescence fused into the level's second substep and in a launch of its
+ * own (lbm_set_level_fusion), with lbm_time_launches over one warm-up and
+ * n_steps >= 1 coarse steps, in two passes over all candidates (each
+ * candidate keeps its faster pass), keeps for every level the candidate
+ * with the smallest mean step time of that level (its two substeps plus the
+ * coarser level's coalescence launch where that runs on its own), and
+ * applies it.  With TRT (lbm_set_trt_force) a persistent candidate runs one
+ * workgroup per work unit.
+ * result[5 * L + {0, 1, 2, 3, 4}] = chosen persistent, order, split, fusion
+ * and that level's mean time per level step in ms.  The PDF state is saved before
  * and restored after (device memory equal to the forest's PDF storage is
  * allocated for it; LBM_E_OOM otherwise), so the simulation is left exactly
  * where it was.  Synchronizes. */

@@ -137,7 +137,7 @@ int make_levels(int n, size_t s, const std::vector<LevelTables>& tabs, std::vect
     if ((rc = upload(v.allocs, &v.fine_index, t.fine_index))) return rc;
     if ((rc = upload(v.allocs, &v.fine_nbr, t.fine_nbr))) return rc;
     if ((rc = upload(v.allocs, &v.fine_slot, t.fine_slot))) return rc;
-    if ((rc = upload(v.allocs, &v.pairs, t.coal_pairs))) return rc;
+    if ((rc = upload(v.allocs, &v.cells, t.coal_cells))) return rc;
     if ((rc = upload(v.allocs, &v.chunks, t.coal_chunks))) return rc;
     v.nchunks = int32_t(t.coal_chunks.size() / 4);
     if (v.nchunks) {
@@ -259,6 +259,8 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   }
   a.interp = f->interp ? 1 : 0;
   a.par_nbr = L > 0 ? f->lv[L - 1].nbr : nullptr;
+  a.fc = CoalArgs{};  // no coalescence in this launch (fuse_coalescence may add one)
+  a.fc_stride = 0;
   if (L + 1 < nlev && d.nchunks > 0) {
     Op c;
     c.level = L;
@@ -271,7 +273,7 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
     c.coal.out_x = d.coal_x;
     c.coal.fine0_x = fine0_x;
     c.coal.fine1_x = fine1_x;
-    c.coal.pairs = d.pairs;
+    c.coal.cells = d.cells;
     c.coal.chunks = d.chunks;
     c.coal.nchunks = d.nchunks;
     c.coal.nbr = d.nbr;
@@ -331,6 +333,37 @@ int grid_for(const lbm_forest* f, int level, int nwork) {
   const int units = nwork * f->lv[level].split;
   if (p <= 0) return units;
   return std::max(1, std::min(units, f->num_cu * p));
+}
+
+// Moves each coalescence launch into the launch just before it, the finer
+// level's second substep, where that is a sweep with one workgroup per work
+// unit and the homogeneous explosion: its chunks then run while that sweep
+// streams (SweepArgs::fc).  The chunks read the finer level's states at t
+// and t + 1/2 and this level's current state, none of which the second
+// substep writes, and they are done when the launch ends, before this
+// level's sweep reads them.  Left as launches of their own: where the finer
+// level's fusion is off (lbm_set_level_fusion; the autotuner picks it per
+// level), on the per-block schedule, and where the finer level runs a
+// persistent grid, the interpolated explosion or in place.
+bool level_fuses(const lbm_forest* f, int L) { return f->lv[L].fuse >= 0 ? f->lv[L].fuse != 0 : f->fuse; }
+
+void fuse_coalescence(const lbm_forest* f, std::vector<Op>& ops) {
+  if (f->interp) return;
+  std::vector<Op> out;
+  out.reserve(ops.size());
+  for (const Op& op : ops) {
+    if (op.kind == Op::kCoalesce && !out.empty()) {
+      Op& host = out.back();
+      if (host.kind == Op::kSweep && host.level == op.level + 1 && host.args.substep == 2 && host.args.nwork > 0 &&
+          host.args.fc.nchunks == 0 && level_fuses(f, host.level) &&
+          grid_for(f, host.level, host.args.nwork) >= host.args.nwork * f->lv[host.level].split) {
+        host.args.fc = op.coal;
+        continue;
+      }
+    }
+    out.push_back(op);
+  }
+  ops.swap(out);
 }
 
 hipError_t launch_level(const lbm_forest* f, const Op& op) {
@@ -925,6 +958,31 @@ int lbm_set_coalescence_check(lbm_forest* f, int on) {
   return LBM_OK;
 }
 
+int lbm_set_coalescence_fusion(lbm_forest* f, int on) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  if (on != 0 && on != 1) return fail(LBM_E_INVALID, "on must be 0 or 1");
+  f->fuse = on != 0;
+  for (auto& v : f->lv) v.fuse = -1;
+  invalidate_graphs(f);
+  return LBM_OK;
+}
+
+int lbm_set_level_fusion(lbm_forest* f, int level, int on) {
+  if (!f) return fail(LBM_E_INVALID, "null pointer");
+  if (level < 0 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
+  if (on < -1 || on > 1) return fail(LBM_E_INVALID, "on must be -1, 0 or 1");
+  f->lv[level].fuse = on;
+  invalidate_graphs(f);
+  return LBM_OK;
+}
+
+int lbm_get_level_fusion(const lbm_forest* f, int level, int* on) {
+  if (!f || !on) return fail(LBM_E_INVALID, "null pointer");
+  if (level < 0 || level >= int(f->lv.size())) return fail(LBM_E_INVALID, "level out of range");
+  *on = level_fuses(f, level) ? 1 : 0;
+  return LBM_OK;
+}
+
 int lbm_coalescence_check(lbm_forest* f, double out[3]) {
   if (!f || !out) return fail(LBM_E_INVALID, "null pointer");
   HIP_TRY(hipSetDevice(f->device));
@@ -1014,28 +1072,37 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
                                    {1, 1, 1}, {2, 0, 1}, {2, 1, 1}, {4, 0, 1}, {4, 1, 1}, {8, 0, 1}, {8, 1, 1}};
     const int ncand = int(sizeof(kCand) / sizeof(kCand[0]));
     std::vector<double> best(nl, 1e300);
-    std::vector<int> bp(nl, 0), bo(nl, 0), bs(nl, 1);
-    std::vector<double> ms(2 * nl);
-    std::vector<int64_t> cnt(2 * nl);
+    std::vector<int> bp(nl, 0), bo(nl, 0), bs(nl, 1), bf(nl, 1);
+    std::vector<double> ms(2 * nl), cms(nl);
+    std::vector<int64_t> cnt(2 * nl), ccnt(nl);
     // two passes over the candidates, each candidate keeping its faster
     // pass: a drift of the clocks during the search then favours no candidate
+    // every shape is timed with the coarser level's coalescence inside the
+    // level's second substep (fuse 1) and in a launch of its own (fuse 0)
     for (int pass = 0; pass < 2; ++pass) {
-      for (int c = 0; c < ncand; ++c) {
+      for (int c = 0; c < 2 * ncand; ++c) {
+        const int* cand = kCand[c / 2];
+        const int fz = 1 - c % 2;
         for (int L = 0; L < nl; ++L) {
-          f->lv[L].persistent = kCand[c][0];
-          f->lv[L].order = kCand[c][1];
-          f->lv[L].split = sweep_split(f->storage, f->n, kCand[c][2]);
+          f->lv[L].persistent = cand[0];
+          f->lv[L].order = cand[1];
+          f->lv[L].split = sweep_split(f->storage, f->n, cand[2]);
+          f->lv[L].fuse = fz;
         }
-        if ((rc = lbm_time_sweeps(f, 1, ms.data(), cnt.data()))) return rc;  // warm-up
-        if ((rc = lbm_time_sweeps(f, n_steps, ms.data(), cnt.data()))) return rc;
+        if ((rc = lbm_time_launches(f, 1, ms.data(), cnt.data(), cms.data(), ccnt.data()))) return rc;  // warm-up
+        if ((rc = lbm_time_launches(f, n_steps, ms.data(), cnt.data(), cms.data(), ccnt.data()))) return rc;
         for (int L = 0; L < nl; ++L) {
-          // mean time of one step of level L: its substeps' mean launch durations
-          const double t = ms[2 * L] + (L > 0 ? ms[2 * L + 1] : 0.0);
+          // mean time of one step of level L: its substeps' mean launch
+          // durations, plus the coarser level's coalescence where it runs as
+          // a launch of its own (where level L's second substep runs it, the
+          // substep's duration holds it)
+          const double t = ms[2 * L] + (L > 0 ? ms[2 * L + 1] + (ccnt[L - 1] ? cms[L - 1] : 0.0) : 0.0);
           if (f->lv[L].nwork > 0 && t < best[L]) {
             best[L] = t;
-            bp[L] = kCand[c][0];
-            bo[L] = kCand[c][1];
+            bp[L] = cand[0];
+            bo[L] = cand[1];
             bs[L] = f->lv[L].split;
+            bf[L] = fz;
           }
         }
       }
@@ -1044,10 +1111,12 @@ int lbm_autotune(lbm_forest* f, int n_steps, double* result) {
       f->lv[L].persistent = bp[L];
       f->lv[L].order = bo[L];
       f->lv[L].split = bs[L];
-      result[4 * L] = bp[L];
-      result[4 * L + 1] = bo[L];
-      result[4 * L + 2] = bs[L];
-      result[4 * L + 3] = best[L] < 1e300 ? best[L] : 0.0;
+      f->lv[L].fuse = bf[L];
+      result[5 * L] = bp[L];
+      result[5 * L + 1] = bo[L];
+      result[5 * L + 2] = bs[L];
+      result[5 * L + 3] = bf[L];
+      result[5 * L + 4] = best[L] < 1e300 ? best[L] : 0.0;
     }
     for (int L = 0; L < nl; ++L) {
       const LevelDev& v = f->lv[L];
@@ -1090,6 +1159,7 @@ int lbm_step_coarse(lbm_forest* f, int n_steps) {
     std::vector<int> r = f->rot;
     std::vector<Op> ops;
     emit(f, 0, 1, r, nullptr, ops);
+    if (f->schedule != LBM_SCHED_PER_BLOCK) fuse_coalescence(f, ops);
     f->rot_prev = f->rot;
     f->steps_since_state++;
     f->post_lost = f->inplace;
@@ -1158,6 +1228,7 @@ int lbm_time_launches(lbm_forest* f, int n_steps, double* ms, int64_t* launches,
       std::vector<int> r = f->rot;
       std::vector<Op> ops;
       emit(f, 0, 1, r, nullptr, ops);
+      if (f->schedule != LBM_SCHED_PER_BLOCK) fuse_coalescence(f, ops);
       f->rot_prev = f->rot;
       f->steps_since_state++;
       f->post_lost = f->inplace;
@@ -1367,6 +1438,7 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
       nlv[L].persistent = f->lv[L].persistent;
       nlv[L].order = f->lv[L].order;
       nlv[L].split = f->lv[L].split;
+      nlv[L].fuse = f->lv[L].fuse;
     }
     free_levels(f->lv);
     f->lv = std::move(nlv);

@@ -398,6 +398,10 @@ int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>
   // so that neighbouring threads of the coalescence read neighbouring cells.
   // Whether (X, a) is coalesced depends only on X's position class (low
   // face, inside or high face along each axis) and a.
+  if (int64_t(n3) > 65536) {
+    err = "cells per block exceed the 16-bit cell index of the coalescence";
+    return LBM_E_INVALID;
+  }
   std::vector<int> boundary, bclass;  // cells of the block's outer layer, ascending, and their class
   for (int c = 0; c < n3; ++c) {
     const int ijk[3] = {c % n, (c / n) % n, c / (n * n)};
@@ -411,10 +415,10 @@ int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>
   for (int L = 0; L + 1 < nlev; ++L) {
     LevelTables& t = out[L];
     int64_t pairs = 0;
+    std::vector<std::vector<int32_t>> by_row;  // each row's chunk records
     for (int s = 0; s < t.nblocks; ++s) {
       if (!(t.flags[s] & kHasFine)) continue;
       const int row = t.fine_index[s];
-      const int64_t first = int64_t(t.coal_pairs.size());
       uint32_t dirs[27];  // per class: bit a set if (X, a) is coalesced
       for (int cls = 0; cls < 27; ++cls) {
         const int pc[3] = {cls % 3, (cls / 3) % 3, cls / 9};
@@ -440,20 +444,39 @@ int build_level_tables(const Forest& f, int tile_cells, std::vector<LevelTables>
           if (coal) dirs[cls] |= 1u << a;
         }
       }
-      for (int a = 1; a < 19; ++a)
+      std::vector<int32_t> recs;
+      for (int a = 1; a < 19; ++a) {
+        const int64_t first = int64_t(t.coal_cells.size());
         for (size_t q = 0; q < boundary.size(); ++q)
-          if ((dirs[bclass[q]] >> a) & 1u) {
-            t.coal_pairs.push_back((uint32_t(a) << 16) | uint32_t(boundary[q]));
-            ++pairs;
-          }
-      const int64_t end = int64_t(t.coal_pairs.size());
-      for (int64_t b = first; b < end; b += kCoalChunk) {
-        t.coal_chunks.push_back(row);
-        t.coal_chunks.push_back(s);
-        t.coal_chunks.push_back(int32_t(b));
-        t.coal_chunks.push_back(int32_t(std::min<int64_t>(end, b + kCoalChunk)));
+          if ((dirs[bclass[q]] >> a) & 1u) t.coal_cells.push_back(uint16_t(boundary[q]));
+        const int64_t end = int64_t(t.coal_cells.size());
+        pairs += end - first;
+        for (int64_t b = first; b < end; b += kCoalChunk) {
+          const int64_t cnt = std::min<int64_t>(end - b, kCoalChunk);
+          recs.insert(recs.end(), {int32_t(row), int32_t(s), int32_t(b), int32_t(cnt | (int64_t(a) << 16))});
+        }
       }
+      by_row.push_back(std::move(recs));
     }
+    // every row's chunks on one XCD: rows go to the XCD with the fewest
+    // chunks so far, then the per-XCD lists are interleaved (position
+    // p runs on XCD p % kXcds), the shorter ones padded with empty chunks
+    std::vector<std::vector<int32_t>> per_xcd(kXcds);
+    for (const auto& recs : by_row) {
+      int best = 0;
+      for (int x = 1; x < kXcds; ++x)
+        if (per_xcd[x].size() < per_xcd[best].size()) best = x;
+      per_xcd[best].insert(per_xcd[best].end(), recs.begin(), recs.end());
+    }
+    size_t longest = 0;
+    for (const auto& v : per_xcd) longest = std::max(longest, v.size() / 4);
+    for (size_t k = 0; k < longest; ++k)
+      for (int x = 0; x < kXcds; ++x) {
+        if (4 * k < per_xcd[x].size())
+          t.coal_chunks.insert(t.coal_chunks.end(), per_xcd[x].begin() + 4 * k, per_xcd[x].begin() + 4 * k + 4);
+        else
+          t.coal_chunks.insert(t.coal_chunks.end(), {0, 0, 0, 0});
+      }
     t.coalesced_pairs = pairs;
   }
   return LBM_OK;

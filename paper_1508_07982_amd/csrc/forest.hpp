@@ -88,13 +88,15 @@ class Forest {
 constexpr int32_t kFineWall = -2;  // fine_nbr entry beyond a non-periodic end
 
 // Tables of one level, ready to copy to the device.
-// Coalesced pairs per thread of the coalescence launch, and per chunk (one
-// workgroup of 256 threads).  The launch is latency-bound (a chain of
-// dependent loads per workgroup); on the benchmark grids 1 pair per thread
-// ran fastest (level 2 of the sphere shell: 47 us per launch, against 50 us
-// with 2 and 67 us with 4 pairs per thread in FP32).
-constexpr int kCoalPairs = 1;
+// Coalesced pairs per chunk of the coalescence launch (one workgroup, one
+// pair per thread); every chunk holds pairs of one direction only, so that
+// the direction is uniform over the workgroup.
 constexpr int kCoalChunk = 256;
+// Workgroups are dispatched round-robin over the chip's 8 XCDs (workgroup b
+// to XCD b % 8), each with its own L2.  The chunk list is laid out so that
+// all chunks of one block land on one XCD: the block's neighbour tables,
+// which each chunk stages, are then fetched from HBM once.
+constexpr int kXcds = 8;
 
 struct LevelTables {
   int level = 0;
@@ -111,10 +113,12 @@ struct LevelTables {
                                       // non-periodic end
   std::vector<int32_t> work;          // slot * tiles_per_block + tile
   std::vector<int32_t> fine_slot;     // [row]: the slot whose fine_nbr row it is
-  std::vector<uint32_t> coal_pairs;   // coalesced (cell, direction) pairs by fine_nbr row:
-                                      // (direction << 16) | cell
-  std::vector<int32_t> coal_chunks;   // [chunk][4]: fine_nbr row, slot, first pair, end pair (at
-                                      // most kCoalChunk pairs of one row each)
+  std::vector<uint16_t> coal_cells;   // cells of the coalesced (cell, direction) pairs, grouped
+                                      // by fine_nbr row, then by direction
+  std::vector<int32_t> coal_chunks;   // [chunk][4]: fine_nbr row, slot, first pair, count |
+                                      // (direction << 16): at most kCoalChunk pairs of one row
+                                      // and direction; count 0 marks a padding chunk.  All
+                                      // chunks of one row sit at positions equal mod kXcds.
   int64_t coarse_blocks = 0;          // blocks touching level L-1
   int64_t fine_blocks = 0;            // blocks touching level L+1
   int64_t coalesced_pairs = 0;

@@ -7,6 +7,53 @@
 
 namespace lbm {
 
+// Coalescence of level L for one of its substeps (eq. ftoc), run after the
+// finer level's two substeps and before the level-L sweep: for every
+// coalesced pair (X, a) of a slot with finer neighbours, the mean over the 8
+// children of X of what the finer level's second stream pulled into them
+// (with the bounce-back at no-slip walls in the fine ghost layers),
+// written to out[row][a][cell] (block-major like the state, one block per
+// fine_nbr row), or to out_x for a pair that enters through an x face
+// (cell x = 0 with e_a,x = +1, x = n - 1 with e_a,x = -1; x-face layout).
+//
+// Every state buffer has an x-face copy, [slot][10][n^2]: the values that
+// leave each block through its x faces (cell x = 0 for e_a,x = -1, x = n - 1
+// for +1).  Each sweep writes the copy of the buffer it writes, from
+// registers.  The sweep takes the x-edge value of each row end from its x
+// neighbour's copy, and the coalescence its children at x faces; in the
+// state's layout each of these would cost a 128-byte line per element.  A
+// buffer written by anything but a sweep has its copy refreshed by
+// launch_face_copy.
+struct CoalArgs {
+  const void* cur;            // level-L state read by the following sweep (the regular sources)
+  const void* fine0;          // level-(L+1) state at the start of the parent step
+  const void* fine1;          // level-(L+1) state after its first substep
+  void* out;                  // [row][19][n^3]
+  void* out_x;                // [row][10][n^2]
+  const void* fine0_x;        // x-face copies of fine0 and fine1
+  const void* fine1_x;
+  const uint16_t* cells;      // [pair]: the pair's cell, grouped by row, then direction
+  const int32_t* chunks;      // [chunk][4]: fine_nbr row, coarse slot, first pair, count |
+                              // (direction << 16); count 0: nothing to do
+  int32_t nchunks;
+  const int32_t* nbr;         // level-L [slot][27]
+  const int32_t* fine_nbr;    // [row][8][27]
+  const int32_t* fine_slot;   // [row]
+  // accumulation check (null: off): each pair's 8-child sum is also formed
+  // in FP64 from the same loaded values; check[0] and check[1] keep, as the
+  // bit patterns of non-negative doubles, the largest |compute-type mean -
+  // FP64 mean| and the largest ratio of |sum - FP64 sum| to the bound
+  // gamma_7 sum |v| of recursive summation of 8 terms; check[2] counts pairs
+  unsigned long long* check;
+  int* err;                   // error bits (table lookup failures)
+  int32_t interp;             // 1: interpolated explosion of the coarse values the children trace back to
+  int32_t walls;              // 1: the forest has a non-periodic axis (no-slip walls)
+  // finer level streamed in place (non-null): its values at t and t + 1/2 come
+  // from its save arrays instead of fine0 / fine1 (see inplace_save.hpp)
+  const void* save_t;         // saves of the finer state at the start of its parent step
+  const void* save_half;      // saves of the finer state after its first substep
+};
+
 // Arguments of one level substep of the fused sweep.  PDF buffers are
 // block-major: element (a, slot, cell) sits at (19 slot + a) n^3 + cell.
 // Levels L >= 1 keep three buffers: the state at the start of the parent
@@ -41,55 +88,17 @@ struct SweepArgs {
   double accel64[3];          // a_L (FP64 form)
   int32_t interp;             // 1: interpolated explosion (see interp_value in lattice.hpp)
   const int32_t* par_nbr;     // level-(L-1) [slot][27] (the parents' neighbours, for interp)
+  // the coalescence of level L - 1 run by this launch (a second substep of
+  // level L with one workgroup per work unit and the homogeneous explosion):
+  // fc.nchunks workgroups, one per chunk, interleaved with the sweep's work
+  // units (launch_sweep sets the spacing); fc.nchunks = 0: none.  The chunks
+  // read only level L's states at t and t + 1/2 and level L - 1's current
+  // state, none of which this substep writes.
+  CoalArgs fc;
+  int32_t fc_stride;
 };
 
 enum ErrBits : int { kErrNoSource = 1, kErrNoChild = 2 };
-
-// Coalescence of level L for one of its substeps (eq. ftoc), run after the
-// finer level's two substeps and before the level-L sweep: for every
-// coalesced pair (X, a) of a slot with finer neighbours, the mean over the 8
-// children of X of what the finer level's second stream pulled into them
-// (with the bounce-back at no-slip walls in the fine ghost layers),
-// written to out[row][a][cell] (block-major like the state, one block per
-// fine_nbr row), or to out_x for a pair that enters through an x face
-// (cell x = 0 with e_a,x = +1, x = n - 1 with e_a,x = -1; x-face layout).
-//
-// Every state buffer has an x-face copy, [slot][10][n^2]: the values that
-// leave each block through its x faces (cell x = 0 for e_a,x = -1, x = n - 1
-// for +1).  Each sweep writes the copy of the buffer it writes, from
-// registers.  The sweep takes the x-edge value of each row end from its x
-// neighbour's copy, and the coalescence its children at x faces; in the
-// state's layout each of these would cost a 128-byte line per element.  A
-// buffer written by anything but a sweep has its copy refreshed by
-// launch_face_copy.
-struct CoalArgs {
-  const void* cur;            // level-L state read by the following sweep (the regular sources)
-  const void* fine0;          // level-(L+1) state at the start of the parent step
-  const void* fine1;          // level-(L+1) state after its first substep
-  void* out;                  // [row][19][n^3]
-  void* out_x;                // [row][10][n^2]
-  const void* fine0_x;        // x-face copies of fine0 and fine1
-  const void* fine1_x;
-  const uint32_t* pairs;      // [pair]: (direction << 16) | cell, grouped by row
-  const int32_t* chunks;      // [chunk][4]: fine_nbr row, coarse slot, first pair, end pair
-  int32_t nchunks;
-  const int32_t* nbr;         // level-L [slot][27]
-  const int32_t* fine_nbr;    // [row][8][27]
-  const int32_t* fine_slot;   // [row]
-  // accumulation check (null: off): each pair's 8-child sum is also formed
-  // in FP64 from the same loaded values; check[0] and check[1] keep, as the
-  // bit patterns of non-negative doubles, the largest |compute-type mean -
-  // FP64 mean| and the largest ratio of |sum - FP64 sum| to the bound
-  // gamma_7 sum |v| of recursive summation of 8 terms; check[2] counts pairs
-  unsigned long long* check;
-  int* err;                   // error bits (table lookup failures)
-  int32_t interp;             // 1: interpolated explosion of the coarse values the children trace back to
-  int32_t walls;              // 1: the forest has a non-periodic axis (no-slip walls)
-  // finer level streamed in place (non-null): its values at t and t + 1/2 come
-  // from its save arrays instead of fine0 / fine1 (see inplace_save.hpp)
-  const void* save_t;         // saves of the finer state at the start of its parent step
-  const void* save_half;      // saves of the finer state after its first substep
-};
 
 hipError_t launch_coalesce(int storage, int n, const CoalArgs& a, hipStream_t stream);
 

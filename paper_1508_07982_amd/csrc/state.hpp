@@ -27,14 +27,15 @@ struct LevelDev {
   int32_t* fine_index = nullptr;
   int32_t* fine_nbr = nullptr;
   int32_t* fine_slot = nullptr;
-  uint32_t* pairs = nullptr;    // coalesced pairs
-  int32_t* chunks = nullptr;    // coalescence work: fine_nbr row, slot, first pair, end pair
+  uint16_t* cells = nullptr;    // cells of the coalesced pairs
+  int32_t* chunks = nullptr;    // coalescence work: fine_nbr row, slot, first pair, count | direction << 16
   int32_t nchunks = 0;
   void* coal = nullptr;         // coalesced values [fine row][19][n^3]
   void* coal_x = nullptr;       // coalesced values of x-crossing pairs [fine row][10][n^2]
   void* xface[3] = {nullptr, nullptr, nullptr};  // x-face copy of each buffer [slot][10][n^2]
   int32_t* work = nullptr;      // work tiles in canonical order
   int persistent = -1;          // launch shape of this level; -1: the forest-wide setting
+  int fuse = -1;                // 1: its second substep runs level L-1's coalescence (0 not; -1 forest-wide)
   int order = 0;                // 0 canonical unit order, 1 XCD-grouped (SweepArgs::xcd)
   int split = 1;                // workgroups per work tile (1, 2 or 4; see sweep_split)
   double omega = 0.0;           // omega_L (SRT) or lambda_e,L (TRT)
@@ -85,6 +86,7 @@ struct lbm_forest {
   std::map<std::vector<int>, hipGraphExec_t> graphs;
   int* d_err = nullptr;
   bool coal_check = false;                  // FP64 accumulation check of the coalescence
+  bool fuse = true;                         // forest-wide LevelDev::fuse
   bool interp = false;                      // interpolated explosion (lbm_set_explosion_interpolation)
   bool inplace = false;                     // in-place streaming (lbm_set_inplace): level 0 keeps one buffer
   int layout = 0;                           // its layout (InplaceLayout in inplace.hpp)

@@ -36,6 +36,7 @@
 // direction and the 19 rows of a tile lie inside one block's storage.
 #pragma once
 
+#include "coalesce.hpp"
 #include "forest.hpp"
 #include "kernels.hpp"
 #include "lattice.hpp"
@@ -713,12 +714,31 @@ __device__ __forceinline__ int xcd_unit(int b, int n) {
 
 // One workgroup per work unit (PERSIST = false), or a fixed grid of
 // workgroups looping over the units (PERSIST = true).  TRT: the TRT
-// collision with a body force instead of SRT.
-template <typename S, int N, bool PERSIST, int SPLIT, bool TRT = false, bool INTERP = false>
+// collision with a body force instead of SRT.  FUSED: the launch also runs
+// the coarser level's coalescence (SweepArgs::fc), one chunk per workgroup
+// at every fc_stride-th position of the first fc.nchunks * fc_stride; the
+// other workgroups take the work units in order.  The chunks thus run
+// while the sweep streams, instead of in a launch of their own; with
+// fc_stride = 1 mod 8, chunk j runs on XCD j mod 8 as in a launch of its
+// own (see kXcds).
+template <typename S, int N, bool PERSIST, int SPLIT, bool TRT = false, bool INTERP = false, bool FUSED = false>
 __global__ void __launch_bounds__((Geo<S, N>::T / SPLIT)) sweep_kernel(SweepArgs a) {
   const int units = a.nwork * SPLIT;
   if (!PERSIST) {
-    const int b = int(blockIdx.x);
+    int b = int(blockIdx.x);
+    if constexpr (FUSED) {
+      const int K = a.fc.nchunks, s = a.fc_stride;
+      if (b % s == s - 1 && b / s < K) {
+        __shared__ int32_t fns[8 * 27];
+        __shared__ int32_t nbs[27];
+        if (a.fc.walls)
+          coalesce_chunk<S, N, false, true>(a.fc, b / s, fns, nbs);
+        else
+          coalesce_chunk<S, N, false, false>(a.fc, b / s, fns, nbs);
+        return;
+      }
+      b -= min(K, (b + 1) / s);
+    }
     sweep_item<S, N, SPLIT, TRT, INTERP>(a, a.xcd ? xcd_unit(b, units) : b);
     return;
   }
@@ -746,7 +766,9 @@ int sweep_split_t(int n, int requested) {
 // Launch of one level substep for storage type S: `split` must be the value
 // sweep_split_t returns, grid >= nwork * split launches one workgroup per
 // work unit, a smaller grid a persistent one (SRT only: the TRT form always
-// launches one workgroup per work unit).
+// launches one workgroup per work unit).  With a.fc.nchunks > 0 (one
+// workgroup per work unit and the homogeneous explosion only) the launch
+// also runs those coalescence chunks, spread evenly over the grid.
 template <typename S>
 hipError_t launch_sweep_t(int n, const SweepArgs& a, int grid, int split, hipStream_t stream) {
   auto go = [&](auto nn, auto ss) -> hipError_t {
@@ -755,6 +777,20 @@ hipError_t launch_sweep_t(int n, const SweepArgs& a, int grid, int split, hipStr
       return hipErrorInvalidValue;
     } else {
       constexpr int T = Geo<S, N>::T / SPLIT;
+      if (a.fc.nchunks > 0) {
+        const int units = a.nwork * SPLIT, K = a.fc.nchunks;
+        if (a.interp || grid < units || units < 1) return hipErrorInvalidValue;
+        // chunk positions j * s + s - 1 (j < K) stay inside the grid of
+        // units + K workgroups for any s <= units / K + 1
+        const int q = units / K;
+        SweepArgs f = a;
+        f.fc_stride = q >= 8 ? 8 * (q / 8) + 1 : 1;
+        if (a.trt)
+          hipLaunchKernelGGL((sweep_kernel<S, N, false, SPLIT, true, false, true>), dim3(units + K), dim3(T), 0, stream, f);
+        else
+          hipLaunchKernelGGL((sweep_kernel<S, N, false, SPLIT, false, false, true>), dim3(units + K), dim3(T), 0, stream, f);
+        return hipGetLastError();
+      }
       if (a.interp) {
         // the interpolated explosion: one workgroup of the full tile per work tile
         constexpr int T1 = Geo<S, N>::T;

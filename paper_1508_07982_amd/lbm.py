@@ -74,6 +74,9 @@ _SIGNATURES = {
     "lbm_mass": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
     "lbm_set_schedule": [ctypes.c_void_p, ctypes.c_int],
     "lbm_set_coalescence_check": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_set_coalescence_fusion": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_set_level_fusion": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
+    "lbm_get_level_fusion": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
     "lbm_set_explosion_interpolation": [ctypes.c_void_p, ctypes.c_int],
     "lbm_set_inplace": [ctypes.c_void_p, ctypes.c_int],
     "lbm_get_inplace": [ctypes.c_void_p, ctypes.c_void_p],
@@ -301,6 +304,21 @@ class Forest:
     def set_coalescence_check(self, on: bool = True):
         _check(self._lib.lbm_set_coalescence_check(self._h, int(bool(on))))
 
+    def set_coalescence_fusion(self, on: bool = True):
+        """Every level: the coarser level's coalescence inside the level's
+        second-substep launch (on, the default) or in a launch of its own
+        (off); results are bitwise equal."""
+        _check(self._lib.lbm_set_coalescence_fusion(self._h, int(bool(on))))
+
+    def set_level_fusion(self, level: int, on: int):
+        """The same for one level (on = 1, 0, or -1: the forest-wide setting)."""
+        _check(self._lib.lbm_set_level_fusion(self._h, int(level), int(on)))
+
+    def get_level_fusion(self, level: int) -> bool:
+        v = ctypes.c_int()
+        _check(self._lib.lbm_get_level_fusion(self._h, int(level), ctypes.byref(v)))
+        return bool(v.value)
+
     def coalescence_check(self) -> dict:
         """FP64 accumulation-check figures since the last call (reset)."""
         out = np.zeros(3)
@@ -370,30 +388,31 @@ class Forest:
         return p.value, o.value, s.value
 
     def autotune(self, n_steps=2, cache=None):
-        """Pick each level's launch shape by timing; returns a list of
-        {level, persistent, order, split, ms_per_level_step}.  With `cache`
-        (a JSON file path) a shape stored for the same storage form, block
-        size, level and block count is applied without timing, and new
-        results are stored."""
+        """Pick each level's launch shape and coalescence fusion by timing;
+        returns a list of {level, persistent, order, split, fuse,
+        ms_per_level_step}.  With `cache` (a JSON file path) a choice stored
+        for the same storage form, block size, level and block count is
+        applied without timing, and new results are stored."""
         key = [f"{self.storage}/n{self.n}/L{L}/b{self.num_blocks(L)}" for L in range(self.num_levels)]
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as fh:
                 table = json.load(fh)
-        if cache and all(k in table for k in key):
+        if cache and all(k in table and "fuse" in table[k] for k in key):
             out = []
             for L, k in enumerate(key):
                 e = table[k]
                 self.set_level_launch(L, e["persistent"], e["order"], e["split"])
+                self.set_level_fusion(L, e["fuse"])
                 out.append(dict(e, level=L, cached=True))
             return out
-        res = np.zeros(4 * self.num_levels)
+        res = np.zeros(5 * self.num_levels)
         _check(self._lib.lbm_autotune(self._h, int(n_steps), _ptr(res)))
-        out = [{"level": L, "persistent": int(res[4 * L]), "order": int(res[4 * L + 1]), "split": int(res[4 * L + 2]),
-                "ms_per_level_step": float(res[4 * L + 3])} for L in range(self.num_levels)]
+        out = [{"level": L, "persistent": int(res[5 * L]), "order": int(res[5 * L + 1]), "split": int(res[5 * L + 2]),
+                "fuse": int(res[5 * L + 3]), "ms_per_level_step": float(res[5 * L + 4])} for L in range(self.num_levels)]
         if cache:
             for L, k in enumerate(key):
-                table[k] = {c: out[L][c] for c in ("persistent", "order", "split", "ms_per_level_step")}
+                table[k] = {c: out[L][c] for c in ("persistent", "order", "split", "fuse", "ms_per_level_step")}
             with open(cache, "w") as fh:
                 json.dump(table, fh, indent=1, sort_keys=True)
         return out

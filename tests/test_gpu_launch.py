@@ -60,6 +60,7 @@ def test_autotune_restores_state_and_applies_choice():
     assert len(res) == g.num_levels
     for r in res:
         assert r["persistent"] in (0, 1, 2, 4, 8) and r["order"] in (0, 1) and r["split"] in (1, 2, 4)
+        assert r["fuse"] in (0, 1) and g.get_level_fusion(r["level"]) == bool(r["fuse"])
         assert r["ms_per_level_step"] > 0
         assert g.get_level_launch(r["level"]) == (r["persistent"], r["order"], r["split"])
     g.step_coarse(2)
@@ -76,8 +77,9 @@ def test_autotune_cache_reproduces_choice(tmp_path):
     again = g.autotune(n_steps=1, cache=cache)
     assert all(r.get("cached") for r in again)
     for a, b in zip(first, again):
-        assert (a["persistent"], a["order"], a["split"]) == (b["persistent"], b["order"], b["split"])
+        assert (a["persistent"], a["order"], a["split"], a["fuse"]) == (b["persistent"], b["order"], b["split"], b["fuse"])
         assert g.get_level_launch(a["level"]) == (a["persistent"], a["order"], a["split"])
+        assert g.get_level_fusion(a["level"]) == bool(a["fuse"])
     g.close()
 
 
