@@ -8,7 +8,8 @@
 //   - (x, a) in the coalescence set (x - e_a, or for an edge direction one
 //     of its axis projections, lies in region(L+1)) -> the mean of the 8
 //     children of x after the finer level's two substeps (eq. ftoc), computed
-//     by the coalescence launch before this sweep;
+//     before this sweep by the coalescence (coalesce.hpp: a launch of its own,
+//     or workgroups of the finer level's second-substep launch);
 //   - source x - e_a inside a level-L block -> that block's value;
 //   - source in the coarser region (a virtual level-L cell of a ghost
 //     layer), reconstructed by a back-trace instead of a stored halo:

@@ -3,6 +3,7 @@
     python -m paper_1508_07982_amd.profiling copy                 # 1 GiB device copy x 3 (counter scale)
     python -m paper_1508_07982_amd.profiling ceiling OUT.txt       # copy and sweep-shape probes
     python -m paper_1508_07982_amd.profiling sweep [--storage f32] [--workload sphere|slab] [--steps 2]
+            [--separate-coalescence]
     python -m paper_1508_07982_amd.profiling trace-summary  RESULTS_DIR OUT.txt --command "..."
             [--storage f32] [--workload sphere|slab]
     python -m paper_1508_07982_amd.profiling traffic-summary COPY_FETCH COPY_WRITE SWEEP_FETCH SWEEP_WRITE OUT.txt
@@ -12,7 +13,10 @@ The sweep workload is the benchmark grid (sphere shell, 4^3 roots of 32^3
 cells, 121.4 M cells) or the slab + sphere grid of the batching form
 (5^3 roots of 16^3 cells, 8.57 M cells) with the launch shape chosen by the
 autotuner, as in bench.py, stepped with one launch per level substep, so
-every sweep dispatch shows up in the trace.  FETCH_SIZE and WRITE_SIZE (KiB
+every sweep dispatch shows up in the trace (a level whose second substep
+runs the coarser coalescence shows that launch as "fused"; with
+--separate-coalescence every coalescence is a launch of its own, as the
+counter passes use it).  FETCH_SIZE and WRITE_SIZE (KiB
 per dispatch) are scaled by what the same counters read for the library's
 copy probe (lbm_probe_copy) of a known byte count; the result is the HBM
 traffic of one finest-level sweep launch.
@@ -42,7 +46,7 @@ def sweep_sources_hash(storage: str = "f32") -> str:
     """Hash of the sweep kernel's sources with comments and blank space
     removed, so that a counter summary stays valid across comment edits."""
     h = hashlib.sha256()
-    for f in ("sweep.hpp", "lattice.hpp", "kernels.hpp", f"sweep_{storage}.hip"):
+    for f in ("sweep.hpp", "coalesce.hpp", "lattice.hpp", "kernels.hpp", f"sweep_{storage}.hip"):
         with open(os.path.join(HERE, "csrc", f)) as fh:
             text = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
         code = [" ".join(line.split("//", 1)[0].split()) for line in text.splitlines()]
@@ -115,7 +119,7 @@ def write_ceilings(out_path: str, command: str):
     print(open(out_path).read(), flush=True)
 
 
-def run_sweep(storage: str, steps: int, workload: str = "sphere"):
+def run_sweep(storage: str, steps: int, workload: str = "sphere", separate: bool = False):
     sys.path.insert(0, ROOT)
     from paper_1508_07982_amd import lbm
     from paper_1508_07982_amd import workloads as W
@@ -127,7 +131,10 @@ def run_sweep(storage: str, steps: int, workload: str = "sphere"):
     g.init_pdfs(rho, u)
     del rho, u
     launch = g.autotune(2)
-    print("launch per level", [(r["persistent"], r["order"]) for r in launch], flush=True)
+    if separate:  # every coalescence in a launch of its own (counter passes)
+        g.set_coalescence_fusion(False)
+    print("launch per level (persistent, order, split, fuse)",
+          [(r["persistent"], r["order"], r["split"], 0 if separate else r["fuse"]) for r in launch], flush=True)
     g.mass()  # marks the start of the measured phase in the dispatch list
     g.step_coarse(steps)
     g.synchronize()
@@ -161,6 +168,14 @@ def _units_per_tile(name):
     return int(parts[3]) if len(parts) >= 4 and parts[3].isdigit() else 1
 
 
+def _fused(name):
+    """Whether a sweep dispatch also runs coalescence chunks (its last
+    template argument)."""
+    inner = name.split("<", 1)[1].split(">", 1)[0] if "<" in name else ""
+    parts = [p.strip() for p in inner.split(",")]
+    return len(parts) >= 7 and parts[6] == "true"
+
+
 def _measured_from(db):
     """Dispatch id of the first reduction kernel (the start of the measured
     phase), or 0 if there is none."""
@@ -183,7 +198,9 @@ def trace_summary(results: str, out: str, command: str, storage: str = "f32", wo
     per_level = {}
     for name, dur, gx, wx, did in rows:
         if "sweep_kernel" in name and did > first:
-            L = level_of_grid.get(gx // max(wx, 1) // _units_per_tile(name))
+            # a launch that also runs coalescence chunks has a grid of its
+            # own size: "fused" instead of a level
+            L = "fused" if _fused(name) else level_of_grid.get(gx // max(wx, 1) // _units_per_tile(name))
             per_level.setdefault((name.rsplit("(", 1)[0], L), []).append(dur)
     with open(out, "w") as fh:
         fh.write(f"# rocprofv3 --kernel-trace --stats summary\n# command: {command}\n")
@@ -195,7 +212,7 @@ def trace_summary(results: str, out: str, command: str, storage: str = "f32", wo
         fh.write(f"\n# measured phase (dispatches after the first reduce_kernel, id {first}): sweep launches by\n"
                  "# level (level from the grid size = work tiles of that level times the workgroups per tile;\n"
                  "# None = persistent grid)\n")
-        for (k, L), v in sorted(per_level.items(), key=lambda kv: (kv[0][0], -1 if kv[0][1] is None else kv[0][1])):
+        for (k, L), v in sorted(per_level.items(), key=lambda kv: (kv[0][0], str(kv[0][1]))):
             fh.write(f"{k[:60]:60s} level {L}: {len(v):5d} launches, avg {sum(v) / len(v) / 1e3:10.2f} us\n")
     print(open(out).read())
 
@@ -221,7 +238,7 @@ def traffic_summary(copy_fetch, copy_write, sweep_fetch, sweep_write, out, comma
         return [v for n, v, g, w, d in db.execute(
             "select p.name, p.counter_value, k.grid_x, k.workgroup_x, k.dispatch_id from pmc_events p join kernels k "
             "on p.dispatch_id = k.dispatch_id where p.counter_name = ?", (counter,)) if "sweep_kernel" in n
-            and g // max(w, 1) // _units_per_tile(n) == tiles[Lf] and d > first]
+            and not _fused(n) and g // max(w, 1) // _units_per_tile(n) == tiles[Lf] and d > first]
     fin_f = finest(sweep_fetch, "FETCH_SIZE")
     fin_w = finest(sweep_write, "WRITE_SIZE")
     if not fin_f or not fin_w:
@@ -287,6 +304,7 @@ def main():
     s.add_argument("--storage", default="f32")
     s.add_argument("--steps", type=int, default=2)
     s.add_argument("--workload", default="sphere", choices=["sphere", "slab"])
+    s.add_argument("--separate-coalescence", action="store_true")
     t = sub.add_parser("trace-summary")
     t.add_argument("results")
     t.add_argument("out")
@@ -304,7 +322,7 @@ def main():
     elif a.cmd == "ceiling":
         write_ceilings(a.out, a.command)
     elif a.cmd == "sweep":
-        run_sweep(a.storage, a.steps, a.workload)
+        run_sweep(a.storage, a.steps, a.workload, a.separate_coalescence)
     elif a.cmd == "trace-summary":
         trace_summary(a.results, a.out, a.command, a.storage, a.workload)
     else:
