@@ -135,7 +135,7 @@ __device__ __forceinline__ void pair_sources(const CoalArgs& c, const int32_t* f
       if (c.save_half)
         p = static_cast<const S*>(c.save_half) + save_index<N>(uint32_t(fy), A, lx, yy & (N - 1), yz & (N - 1));
       else
-        p = xcopy && lx == xout ? static_cast<const S*>(c.fine1_x) + xface_index_rt<N>(A, uint32_t(fy), uint32_t(jk))
+        p = xcopy && lx == xout ? static_cast<const S*>(c.fine1_x) + xface_index_rt<S, N>(A, uint32_t(fy), uint32_t(jk))
                                 : static_cast<const S*>(c.fine1) + pdf_index<N>(A, uint32_t(fy), uint32_t(lx + N * jk));
     } else if (WALLS && fy == kFineWall) {
       const int wx = cx + ox + EX, wy = cy + oy + EY, wz = cz + oz + EZ;
@@ -157,7 +157,7 @@ __device__ __forceinline__ void pair_sources(const CoalArgs& c, const int32_t* f
       if (c.save_t)
         p = static_cast<const S*>(c.save_t) + save_index<N>(uint32_t(fz), A, lx, zy & (N - 1), zz & (N - 1));
       else
-        p = xcopy && lx == xout ? static_cast<const S*>(c.fine0_x) + xface_index_rt<N>(A, uint32_t(fz), uint32_t(jk))
+        p = xcopy && lx == xout ? static_cast<const S*>(c.fine0_x) + xface_index_rt<S, N>(A, uint32_t(fz), uint32_t(jk))
                                 : static_cast<const S*>(c.fine0) + pdf_index<N>(A, uint32_t(fz), uint32_t(lx + N * jk));
     } else if (WALLS && fz == kFineWall) {
       if (INTERP) {
@@ -223,7 +223,7 @@ __device__ __forceinline__ void coalesce_chunk(const CoalArgs& c, int chunk, int
       // a pair entering through an x face goes to the x-face layout
       const int EX = ex(A);
       S* o = EX != 0 && i == (EX > 0 ? 0 : N - 1)
-                 ? static_cast<S*>(c.out_x) + xface_index_rt<N>(A, uint32_t(row), uint32_t(j + N * k))
+                 ? static_cast<S*>(c.out_x) + xface_index_rt<S, N>(A, uint32_t(row), uint32_t(j + N * k))
                  : static_cast<S*>(c.out) + pdf_index<N>(A, uint32_t(row), uint32_t(cell));
       Form<S>::st(o, sum * C(0.125));
     }

@@ -100,7 +100,7 @@ __device__ __forceinline__ void odd_issue(const InplaceArgs& a, const SlotCache&
     wall |= uint32_t(at_end && nbx < 0) << A;
     // f*_A of the x neighbour's end cell: the value leaving it through its x face
     const int eb = nbx >= 0 ? nbx : slot;
-    edge[xdir_index(A)] = Form<S>::ld(static_cast<const S*>(a.face) + xface_index<N, A>(uint32_t(eb), row / N));
+    edge[xdir_index(A)] = Form<S>::ld(static_cast<const S*>(a.face) + xface_index<S, N, A>(uint32_t(eb), row / N));
   }
 }
 
@@ -160,7 +160,7 @@ __device__ __forceinline__ void odd_walls(const InplaceArgs& a, const SlotCache&
       // row may overwrite that location during this launch)
       if (cells)
         h[A][EX == 1 ? 0 : W - 1] =
-            Form<S>::ld(static_cast<const S*>(a.face) + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)));
+            Form<S>::ld(static_cast<const S*>(a.face) + xface_index<S, N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)));
     }
   }
   if constexpr (A + 1 < 19) odd_walls<S, N, A + 1>(a, sc, slot, cell0, i0, j, k, wall, h);
@@ -202,7 +202,7 @@ __device__ __forceinline__ void odd_store(const InplaceArgs& a, const SlotCache&
     Vec<S>::store(buf + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(cell0)), h[A]);
     if constexpr (EX != 0)
       if (leaving_lane)  // the end cell's reflection enters through its own x face
-        Form<S>::st(entry + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)), h[A][END]);
+        Form<S>::st(entry + xface_index<S, N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)), h[A][END]);
     return;
   }
   S* __restrict__ dst = buf + pdf_index<N>(A, uint32_t(nbd), row + uint32_t(i0));
@@ -213,9 +213,9 @@ __device__ __forceinline__ void odd_store(const InplaceArgs& a, const SlotCache&
     if (leaving_lane) {
       const int nbx = pick<EX, EY, EZ>(sc, true, by, bz);
       if (nbx >= 0)
-        Form<S>::st(entry + xface_index<N, A>(uint32_t(nbx), row / N), h[A][END]);
+        Form<S>::st(entry + xface_index<S, N, A>(uint32_t(nbx), row / N), h[A][END]);
       else  // an x wall: the reflection enters through the cell's own face
-        Form<S>::st(entry + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)), h[A][END]);
+        Form<S>::st(entry + xface_index<S, N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)), h[A][END]);
     }
   }
 }
@@ -262,7 +262,7 @@ __device__ __forceinline__ void odd_specials_ref(const InplaceArgs& a, const Slo
       p[c] = nullptr;
       if (code == kNbrWall) {
         const bool xface = EX != 0 && x == (EX == 1 ? 0 : N - 1);
-        p[c] = xface ? static_cast<const S*>(a.face) + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))
+        p[c] = xface ? static_cast<const S*>(a.face) + xface_index<S, N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))
                      : static_cast<const S*>(a.buf) + pdf_index<N>(A, uint32_t(slot), uint32_t(cell0 + c));
       } else if (code <= kNbrCoarse0) {
         p[c] = iparent<S, N, A>(a, code, sx & (N - 1), sy & (N - 1), sz & (N - 1));
@@ -328,9 +328,9 @@ __device__ __forceinline__ void odd_store_ref(const InplaceArgs& a, const SlotCa
     if (leaving_lane) {
       const int nbx = pick<EX, EY, EZ>(sc, true, by, bz);
       if (nbx >= 0) {
-        Form<S>::st(entry + xface_index<N, A>(uint32_t(nbx), row / N), h[A][END]);
+        Form<S>::st(entry + xface_index<S, N, A>(uint32_t(nbx), row / N), h[A][END]);
       } else {
-        Form<S>::st(entry + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)), h[A][END]);
+        Form<S>::st(entry + xface_index<S, N, opp(A)>(uint32_t(slot), uint32_t(j + N * k)), h[A][END]);
         if (nbx <= kNbrCoarse0) Form<S>::st(save + save_index<N>(uint32_t(slot), A, i0 + END, j, k), h[A][END]);
       }
     }
@@ -446,9 +446,8 @@ __global__ void __launch_bounds__((IGeo<S, N>::T)) inplace_even_kernel(InplaceAr
   const uint32_t jk0 = uint32_t(j + N * k);
 #pragma unroll
   for (int d = 1; d < 19; ++d) {
-    if (ex(d) == 1 && i0 == 0) h[d][0] = Form<S>::ld(e + (uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk0);
-    if (ex(d) == -1 && i0 == N - W)
-      h[d][W - 1] = Form<S>::ld(e + (uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk0);
+    if (ex(d) == 1 && i0 == 0) h[d][0] = Form<S>::ld(e + xface_at<S, N>(uint64_t(slot), xdir_index_rt(d), jk0));
+    if (ex(d) == -1 && i0 == N - W) h[d][W - 1] = Form<S>::ld(e + xface_at<S, N>(uint64_t(slot), xdir_index_rt(d), jk0));
   }
   bool coarse_nbr = false;
   SlotCache sc;
@@ -472,8 +471,8 @@ __global__ void __launch_bounds__((IGeo<S, N>::T)) inplace_even_kernel(InplaceAr
   const uint32_t jk = uint32_t(j + N * k);
 #pragma unroll
   for (int d = 1; d < 19; ++d) {
-    if (ex(d) == 1 && i0 == N - W) Form<S>::st(f + (uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk, h[d][W - 1]);
-    if (ex(d) == -1 && i0 == 0) Form<S>::st(f + (uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk, h[d][0]);
+    if (ex(d) == 1 && i0 == N - W) Form<S>::st(f + xface_at<S, N>(uint64_t(slot), xdir_index_rt(d), jk), h[d][W - 1]);
+    if (ex(d) == -1 && i0 == 0) Form<S>::st(f + xface_at<S, N>(uint64_t(slot), xdir_index_rt(d), jk), h[d][0]);
   }
 }
 
@@ -536,7 +535,7 @@ __device__ __forceinline__ void odd_issue_h8(const InplaceArgs& a, const SlotCac
     const int nbx = pick<-EX, -EY, -EZ>(sc, true, by, bz);
     wall |= uint32_t(at_end && nbx < 0) << A;
     const int eb = nbx >= 0 ? nbx : slot;
-    edge[xdir_index(A)] = static_cast<const uint16_t*>(a.face)[xface_index<N, A>(uint32_t(eb), row / N)];
+    edge[xdir_index(A)] = static_cast<const uint16_t*>(a.face)[xface_index<__half, N, A>(uint32_t(eb), row / N)];
   }
 }
 
@@ -583,7 +582,7 @@ __device__ __forceinline__ void odd_walls_h8(const InplaceArgs& a, const SlotCac
       const bool at_end = EX == 1 ? i0 == 0 : i0 == N - 8;
       if (at_end && pick<-EX, -EY, -EZ>(sc, true, by, bz) < 0) {  // from the x-face copy (see odd_walls)
         const uint32_t v =
-            static_cast<const uint16_t*>(a.face)[xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))];
+            static_cast<const uint16_t*>(a.face)[xface_index<__half, N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))];
         if (EX == 1)
           q[A][0] = (q[A][0] & 0xFFFF0000u) | v;
         else
@@ -620,7 +619,7 @@ __device__ __forceinline__ void odd_store_h8(const InplaceArgs& a, const SlotCac
   if (nbd < 0) {  // the whole destination row lies beyond a wall: every cell reflects
     store_u32x4(buf + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(cell0)), q[A]);
     if constexpr (EX != 0)
-      if (leaving_lane) entry[xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))] = end;
+      if (leaving_lane) entry[xface_index<__half, N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))] = end;
     return;
   }
   uint16_t* __restrict__ dst = buf + pdf_index<N>(A, uint32_t(nbd), row + uint32_t(i0));
@@ -631,9 +630,9 @@ __device__ __forceinline__ void odd_store_h8(const InplaceArgs& a, const SlotCac
     if (leaving_lane) {
       const int nbx = pick<EX, EY, EZ>(sc, true, by, bz);
       if (nbx >= 0)
-        entry[xface_index<N, A>(uint32_t(nbx), row / N)] = end;
+        entry[xface_index<__half, N, A>(uint32_t(nbx), row / N)] = end;
       else
-        entry[xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))] = end;
+        entry[xface_index<__half, N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))] = end;
     }
   }
 }
@@ -671,7 +670,7 @@ __device__ __forceinline__ void odd_specials_ref_h8(const InplaceArgs& a, const 
       p[c] = nullptr;
       if (code == kNbrWall) {
         const bool xface = EX != 0 && x == (EX == 1 ? 0 : N - 1);
-        p[c] = xface ? static_cast<const uint16_t*>(a.face) + xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))
+        p[c] = xface ? static_cast<const uint16_t*>(a.face) + xface_index<__half, N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))
                      : static_cast<const uint16_t*>(a.buf) + pdf_index<N>(A, uint32_t(slot), uint32_t(cell0 + c));
       } else if (code <= kNbrCoarse0) {
         p[c] = reinterpret_cast<const uint16_t*>(iparent<__half, N, A>(a, code, sx & (N - 1), sy & (N - 1), sz & (N - 1)));
@@ -720,9 +719,9 @@ __device__ __forceinline__ void odd_store_ref_h8(const InplaceArgs& a, const Slo
       const uint16_t end = get_half(q[A], END);
       const int nbx = pick<EX, EY, EZ>(sc, true, by, bz);
       if (nbx >= 0) {
-        entry[xface_index<N, A>(uint32_t(nbx), row / N)] = end;
+        entry[xface_index<__half, N, A>(uint32_t(nbx), row / N)] = end;
       } else {
-        entry[xface_index<N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))] = end;
+        entry[xface_index<__half, N, opp(A)>(uint32_t(slot), uint32_t(j + N * k))] = end;
         if (nbx <= kNbrCoarse0) save[save_index<N>(uint32_t(slot), A, i0 + END, j, k)] = end;
       }
     }
@@ -824,9 +823,9 @@ __global__ void __launch_bounds__((IGeo<__half, N>::T)) inplace_even_h8_kernel(I
 #pragma unroll
   for (int d = 1; d < 19; ++d) {  // values that entered through an x face
     if (ex(d) == 1 && i0 == 0)
-      q[d][0] = (q[d][0] & 0xFFFF0000u) | uint32_t(e[(uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk0]);
+      q[d][0] = (q[d][0] & 0xFFFF0000u) | uint32_t(e[xface_at<__half, N>(uint64_t(slot), xdir_index_rt(d), jk0)]);
     if (ex(d) == -1 && i0 == N - 8)
-      q[d][3] = (q[d][3] & 0xFFFFu) | (uint32_t(e[(uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk0]) << 16);
+      q[d][3] = (q[d][3] & 0xFFFFu) | (uint32_t(e[xface_at<__half, N>(uint64_t(slot), xdir_index_rt(d), jk0)]) << 16);
   }
   bool coarse_nbr = false;
   SlotCache sc;
@@ -847,8 +846,8 @@ __global__ void __launch_bounds__((IGeo<__half, N>::T)) inplace_even_h8_kernel(I
   const uint32_t jk = uint32_t(j + N * k);
 #pragma unroll
   for (int d = 1; d < 19; ++d) {
-    if (ex(d) == 1 && i0 == N - 8) f[(uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk] = uint16_t(q[d][3] >> 16);
-    if (ex(d) == -1 && i0 == 0) f[(uint64_t(slot) * kXDirs + xdir_index_rt(d)) * (N * N) + jk] = uint16_t(q[d][0] & 0xFFFFu);
+    if (ex(d) == 1 && i0 == N - 8) f[xface_at<__half, N>(uint64_t(slot), xdir_index_rt(d), jk)] = uint16_t(q[d][3] >> 16);
+    if (ex(d) == -1 && i0 == 0) f[xface_at<__half, N>(uint64_t(slot), xdir_index_rt(d), jk)] = uint16_t(q[d][0] & 0xFFFFu);
   }
 }
 
@@ -897,9 +896,10 @@ __global__ void inplace_entry_merge_kernel(S* __restrict__ buf, const S* __restr
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= count) return;
   const int64_t n2 = int64_t(n) * n;
-  const int64_t slot = e / (kXDirs * n2);
-  const int a = xdir_dir(int((e / n2) % kXDirs));
-  const int64_t jk = e % n2;
+  int64_t slot, jk;
+  int q;
+  xface_decode<S>(e, n, slot, q, jk);
+  const int a = xdir_dir(q);
   const int x = ex(a) > 0 ? 0 : n - 1;
   buf[pdf_at_rt(a, uint64_t(slot) * uint64_t(n2 * n) + uint64_t(x + n * jk), uint64_t(n2 * n))] = entry[e];
 }

@@ -189,13 +189,13 @@ __global__ void __launch_bounds__(kCoalChunk) coalesce_kernel(CoalArgs c) {
 // x-face copy of a buffer (see CoalArgs): one thread per element of xf.
 template <typename S, int N>
 __global__ void face_copy_kernel(const S* buf, S* xf, int64_t count) {
-  constexpr int N2 = N * N;
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= count) return;
-  const int64_t slot = e / (kXDirs * N2);
-  const int A = xdir_dir(int((e / N2) % kXDirs));
-  const int jk = int(e % N2);
-  xf[e] = buf[pdf_index<N>(A, uint64_t(slot), uint32_t((ex(A) < 0 ? 0 : N - 1) + N * jk))];
+  int64_t slot, jk;
+  int q;
+  xface_decode<S>(e, N, slot, q, jk);
+  const int A = xdir_dir(q);
+  xf[e] = buf[pdf_index<N>(A, uint64_t(slot), uint32_t((ex(A) < 0 ? 0 : N - 1) + N * int(jk)))];
 }
 
 template <typename F>

@@ -63,9 +63,13 @@ __host__ __device__ inline uint64_t pdf_at_rt(int a, uint64_t idx, uint64_t n3) 
 // are n apart in the block-major layout, one element per 128-byte line.
 // Where a kernel reads or writes many of them, they are kept in an x-face
 // buffer instead: one element per (row, x direction, y, z), the 10
-// directions with a nonzero x component numbered in direction order,
-// element (row, xdir_index(a), j + n k) at (10 row + xdir_index(a)) n^2 +
-// j + n k.
+// directions with a nonzero x component numbered in direction order.  The
+// (j, k) rows jk = j + n k come in groups of G = 32 bytes / element size
+// (4 in FP64, 8 in FP32, 16 in FP16: the rows of a 64-lane workgroup of the
+// sweep at n = 32), each group holding its rows for all 10 directions, so
+// that the face values one workgroup writes form one contiguous run of whole
+// 64-byte segments: element (row, q, jk) at 10 n^2 row + 10 G (jk / G) +
+// G q + jk mod G.
 constexpr int kXDirs = 10;
 __host__ __device__ __forceinline__ constexpr int xdir_index(int a) {
   int q = 0;
@@ -81,20 +85,40 @@ __host__ __device__ __forceinline__ constexpr int xdir_dir(int q) {
   }
   return a;
 }
+// rows per group of the x-face layout for element type S
+template <typename S>
+__host__ __device__ constexpr int face_rows() {
+  return 32 / int(sizeof(S));
+}
+// element (row, q, jk): q the x-direction number
+template <typename S, int N>
+__host__ __device__ __forceinline__ uint64_t xface_at(uint64_t row, int q, uint32_t jk) {
+  constexpr uint32_t G = uint32_t(face_rows<S>());
+  static_assert((N * N) % G == 0, "a whole number of row groups per face");
+  return row * uint64_t(kXDirs * N * N) + uint64_t(jk / G) * (kXDirs * G) + uint64_t(q) * G + (jk % G);
+}
+// the inverse, for a block size known only at run time: element e -> (row, q, jk)
+template <typename S>
+__host__ __device__ __forceinline__ void xface_decode(int64_t e, int n, int64_t& row, int& q, int64_t& jk) {
+  constexpr int64_t G = face_rows<S>();
+  const int64_t per = int64_t(kXDirs) * n * n, r = e % per;
+  row = e / per;
+  q = int((r % (kXDirs * G)) / G);
+  jk = (r / (kXDirs * G)) * G + r % G;
+}
 // element (row, xdir_index(A), jk), A known at compile time
-template <int N, int A>
+template <typename S, int N, int A>
 __device__ __forceinline__ uint64_t xface_index(uint64_t row, uint32_t jk) {
-  constexpr uint64_t off = uint64_t(xdir_index(A)) * uint64_t(N * N);
-  return row * uint64_t(kXDirs * N * N) + off + jk;
+  return xface_at<S, N>(row, xdir_index(A), jk);
 }
 // the same for a direction known only at run time
 __host__ __device__ __forceinline__ constexpr int xdir_index_rt(int a) {
   // directions 1, 2 and 7 .. 14 have a nonzero x component
   return a <= 2 ? a - 1 : a - 5;
 }
-template <int N>
+template <typename S, int N>
 __device__ __forceinline__ uint64_t xface_index_rt(int a, uint64_t row, uint32_t jk) {
-  return (row * kXDirs + uint64_t(xdir_index_rt(a))) * uint64_t(N * N) + jk;
+  return xface_at<S, N>(row, xdir_index_rt(a), jk);
 }
 static_assert(xdir_index(1) == 0 && xdir_index(2) == 1 && xdir_index(7) == 2 && xdir_index(14) == 9, "x directions");
 constexpr bool xdir_rt_matches() {

@@ -209,7 +209,7 @@ __device__ __forceinline__ const S* coalesced_source(const SweepArgs& a, const S
   constexpr int EX = ex(A);
   if constexpr (EX != 0) {
     if (i == (EX == 1 ? 0 : N - 1))
-      return static_cast<const S*>(a.coal_x) + xface_index<N, A>(uint32_t(sc.fine_row), uint32_t(j + N * k));
+      return static_cast<const S*>(a.coal_x) + xface_index<S, N, A>(uint32_t(sc.fine_row), uint32_t(j + N * k));
   }
   return static_cast<const S*>(a.coal) + pdf_index<N>(A, uint32_t(sc.fine_row), uint32_t(i + N * (j + N * k)));
 }
@@ -247,7 +247,7 @@ __device__ __forceinline__ void issue_dir(const SweepArgs& a, const SlotCache& s
     // the end element of the x neighbour's source row, cell N - 1 (EX = 1)
     // or 0 (EX = -1): a value leaving that block through its x face
     const int eb = SIMPLE || nbx >= 0 ? nbx : slot;
-    edge[xdir_index(A)] = Form<S>::ld(static_cast<const S*>(a.face_cur) + xface_index<N, A>(uint32_t(eb), row / N));
+    edge[xdir_index(A)] = Form<S>::ld(static_cast<const S*>(a.face_cur) + xface_index<S, N, A>(uint32_t(eb), row / N));
   }
 }
 
@@ -426,7 +426,7 @@ __device__ __forceinline__ void collide(C (*h)[W], int c, C om) {
 template <typename S, int N, int SIDE, int A = 1>
 __device__ __forceinline__ void store_face_side(S* __restrict__ f, uint64_t row, uint32_t jk,
                                                 typename Form<S>::C (*h)[Geo<S, N>::W]) {
-  if constexpr (ex(A) == SIDE) Form<S>::st(f + xface_index<N, A>(row, jk), h[A][SIDE < 0 ? 0 : Geo<S, N>::W - 1]);
+  if constexpr (ex(A) == SIDE) Form<S>::st(f + xface_index<S, N, A>(row, jk), h[A][SIDE < 0 ? 0 : Geo<S, N>::W - 1]);
   if constexpr (A + 1 < 19) store_face_side<S, N, SIDE, A + 1>(f, row, jk, h);
 }
 template <typename S, int N>
@@ -548,7 +548,7 @@ __device__ __forceinline__ void issue_dir_h8(const SweepArgs& a, const SlotCache
     const int nbx = pick<-EX, -EY, -EZ>(sc, true, by, bz);
     if (!SIMPLE) odd |= uint32_t(at_end && nbx < 0);
     const int eb = SIMPLE || nbx >= 0 ? nbx : slot;  // as in issue_dir
-    edge[xdir_index(A)] = static_cast<const uint16_t*>(a.face_cur)[xface_index<N, A>(uint32_t(eb), row / N)];
+    edge[xdir_index(A)] = static_cast<const uint16_t*>(a.face_cur)[xface_index<__half, N, A>(uint32_t(eb), row / N)];
   }
 }
 
@@ -623,7 +623,7 @@ template <int N, int SIDE, int A = 1>
 __device__ __forceinline__ void store_face_side_h8(uint16_t* __restrict__ f, uint64_t row, uint32_t jk,
                                                    const uint32_t (*q)[4]) {
   if constexpr (ex(A) == SIDE)
-    f[xface_index<N, A>(row, jk)] = uint16_t(SIDE < 0 ? (q[A][0] & 0xFFFFu) : (q[A][3] >> 16));
+    f[xface_index<__half, N, A>(row, jk)] = uint16_t(SIDE < 0 ? (q[A][0] & 0xFFFFu) : (q[A][3] >> 16));
   if constexpr (A + 1 < 19) store_face_side_h8<N, SIDE, A + 1>(f, row, jk, q);
 }
 
