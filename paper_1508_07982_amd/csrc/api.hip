@@ -178,9 +178,10 @@ void invalidate_graphs(lbm_forest* f) {
 
 // Post-order launch list: substep `substep` of level L, preceded by the two
 // substeps of level L+1.  `r` holds every level's current buffer and is
-// advanced as the launches are emitted.
+// advanced as the launches are emitted.  parent_cur / parent_face: level
+// L-1's state read by level L in this parent step, and its x-face copy.
 void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const void* parent_cur,
-          std::vector<Op>& ops) {
+          const void* parent_face, std::vector<Op>& ops) {
   const LevelDev& d = f->lv[L];
   const int nlev = int(f->lv.size());
   const bool aa = f->inplace && f->inplace_level > 0 && L == f->inplace_level;  // refined, in place
@@ -209,8 +210,8 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   const void* save_half = nullptr;
   if (L + 1 < nlev) {
     const int rf = r[L + 1];
-    emit(f, L + 1, 1, r, cur, ops);
-    emit(f, L + 1, 2, r, cur, ops);
+    emit(f, L + 1, 1, r, cur, d.xface[cb], ops);
+    emit(f, L + 1, 2, r, cur, d.xface[cb], ops);
     const LevelDev& fd = f->lv[L + 1];
     if (f->inplace && L + 1 == f->inplace_level) {
       // the finer level in place: its states at t and t + 1/2 come from its saves
@@ -232,6 +233,7 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
   a.prev = prev;
   a.nxt = nxt;
   a.par = parent_cur;
+  a.par_face = parent_face;
   a.fine0 = fine0;
   a.fine1 = fine1;
   a.work = nullptr;  // every tile of the level, in canonical order
@@ -1158,7 +1160,7 @@ int lbm_step_coarse(lbm_forest* f, int n_steps) {
   for (int s = 0; s < n_steps; ++s) {
     std::vector<int> r = f->rot;
     std::vector<Op> ops;
-    emit(f, 0, 1, r, nullptr, ops);
+    emit(f, 0, 1, r, nullptr, nullptr, ops);
     if (f->schedule != LBM_SCHED_PER_BLOCK) fuse_coalescence(f, ops);
     f->rot_prev = f->rot;
     f->steps_since_state++;
@@ -1227,7 +1229,7 @@ int lbm_time_launches(lbm_forest* f, int n_steps, double* ms, int64_t* launches,
     for (int s = 0; s < n_steps && !(f->inplace && f->inplace_level == 0); ++s) {
       std::vector<int> r = f->rot;
       std::vector<Op> ops;
-      emit(f, 0, 1, r, nullptr, ops);
+      emit(f, 0, 1, r, nullptr, nullptr, ops);
       if (f->schedule != LBM_SCHED_PER_BLOCK) fuse_coalescence(f, ops);
       f->rot_prev = f->rot;
       f->steps_since_state++;
@@ -1320,7 +1322,7 @@ int lbm_regrid(lbm_forest* f, const int8_t* flags, int64_t count) {
     std::vector<Op> ops;
     if (have_post) {
       std::vector<int> r = f->rot_prev;
-      emit(f, 0, 1, r, nullptr, ops);
+      emit(f, 0, 1, r, nullptr, nullptr, ops);
     }
     for (int L = 0; L < nold; ++L) {
       cur[L] = current_buffer(f, L);

@@ -63,6 +63,7 @@ struct SweepArgs {
   const void* prev;           // level-L state at t (second substep only)
   void* nxt;                  // level-L state written
   const void* par;            // level-(L-1) post-collision state (explosion source)
+  const void* par_face;       // its x-face copy (parent values at the parent's x faces)
   const void* fine0;          // level-(L+1) state at the start of its last parent step
   const void* fine1;          // level-(L+1) state after the first of its two substeps
   const int32_t* work;        // work tiles (slot * tiles_per_block + tile), or null: tiles work0 + [0, nwork)

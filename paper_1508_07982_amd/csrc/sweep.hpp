@@ -100,13 +100,21 @@ __device__ __forceinline__ int side(int c) {
 
 // Address of level-L cell (lx, ly, lz) of the virtual block whose neighbour
 // table entry is `code` (< kNbrFine, i.e. inside a level-(L-1) leaf): the
-// parent's post-collision value (homogeneous explosion, eq. ctof).
+// parent's post-collision value (homogeneous explosion, eq. ctof).  A parent
+// cell on the parent block's x face through which direction A leaves it is
+// read from the parent's x-face copy: across an x-face interface all the
+// parents lie there, one per 128-byte line in the block-major buffer and
+// contiguous in the copy.
 template <typename S, int N, int A>
 __device__ __forceinline__ const S* parent_ptr(const SweepArgs& a, int code, int lx, int ly, int lz) {
   constexpr int H = Geo<S, N>::H;
   const int pp = kNbrCoarse0 - code;
   const int oc = pp & 7;
   const int px = (oc & 1 ? H : 0) + (lx >> 1), py = (oc & 2 ? H : 0) + (ly >> 1), pz = (oc & 4 ? H : 0) + (lz >> 1);
+  if constexpr (ex(A) != 0) {
+    if (px == (ex(A) > 0 ? N - 1 : 0))
+      return static_cast<const S*>(a.par_face) + xface_index<S, N, A>(uint32_t(pp >> 3), uint32_t(py + N * pz));
+  }
   return static_cast<const S*>(a.par) + pdf_index<N>(A, uint32_t(pp >> 3), uint32_t(px + N * (py + N * pz)));
 }
 
