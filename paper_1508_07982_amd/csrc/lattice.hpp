@@ -269,37 +269,57 @@ __device__ __forceinline__ C minmod(C p, C q) {
   return p * q <= C(0) ? C(0) : (fabs(p) < fabs(q) ? p : q);
 }
 
+// The reconstruction from P's value f[0] and its face neighbours' f[1 + 2d]
+// (P + e_d) and f[2 + 2d] (P - e_d); b[q] < 0 marks a neighbour that is no
+// interior cell (no slope along that axis).
+template <typename C>
+__device__ __forceinline__ C interp_combine(const C* f, const int* b, int ox, int oy, int oz) {
+  C v = f[0];
+  const int o[3] = {ox, oy, oz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (b[1 + 2 * d] >= 0 && b[2 + 2 * d] >= 0)
+      v += (C(o[d]) - C(0.5)) * C(0.5) * minmod<C>(f[1 + 2 * d] - f[0], f[0] - f[2 + 2 * d]);
+  return v;
+}
+// Offset q of the 7 positions of a reconstruction: P, then P + e_d and
+// P - e_d for d = x, y, z.
+__device__ __forceinline__ int interp_dx(int q, int d) {
+  const int axis = (q - 1) >> 1, s = q == 0 ? 0 : (q & 1 ? 1 : -1);
+  return axis == d ? s : 0;
+}
+
 // P = (px, py, pz): local coordinates relative to the block whose 27-entry
 // neighbour table is `tab` (entry 13: that block), at most one block away
 // (coordinates in [-N, 2N), neighbours included); buf is P's level buffer.
-// A P outside every block of that level sets an error bit and gives 0.
+// A P outside every block of that level sets an error bit and gives 0.  The
+// 7 table entries are loaded together, then the 7 values (a position that is
+// no block reads element 0 instead, and its value is not used), so that a
+// reconstruction costs two memory round trips.
 template <typename S, int N>
 __device__ inline typename Form<S>::C interp_value(const S* buf, const int32_t* tab, int px, int py, int pz, int a,
                                                   int ox, int oy, int oz, int* err) {
   using C = typename Form<S>::C;
   auto sd = [](int c) { return c < 0 ? -1 : (c >= N ? 1 : 0); };
-  auto at = [&](int x, int y, int z, int& ok) -> C {
-    const int b = tab[13 + sd(x) + 3 * sd(y) + 9 * sd(z)];
-    ok = b >= 0;
-    return ok ? Form<S>::ld(buf + pdf_index<N>(a, uint32_t(b), uint32_t((x & (N - 1)) + N * ((y & (N - 1)) + N * (z & (N - 1))))))
-              : C(0);
-  };
-  int ok;
-  const C f0 = at(px, py, pz, ok);
-  if (!ok) {
+  int x[7], y[7], z[7], b[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    x[q] = px + interp_dx(q, 0);
+    y[q] = py + interp_dx(q, 1);
+    z[q] = pz + interp_dx(q, 2);
+    b[q] = tab[13 + sd(x[q]) + 3 * sd(y[q]) + 9 * sd(z[q])];
+  }
+  C f[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q)
+    f[q] = Form<S>::ld(buf + (b[q] >= 0 ? pdf_index<N>(a, uint32_t(b[q]), uint32_t((x[q] & (N - 1)) +
+                                                                                 N * ((y[q] & (N - 1)) + N * (z[q] & (N - 1)))))
+                                        : 0));
+  if (b[0] < 0) {
     atomicOr(err, 1);
     return C(0);
   }
-  C v = f0;
-  const int o[3] = {ox, oy, oz};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int okp, okm;
-    const C fp = at(px + (d == 0), py + (d == 1), pz + (d == 2), okp);
-    const C fm = at(px - (d == 0), py - (d == 1), pz - (d == 2), okm);
-    if (okp && okm) v += (C(o[d]) - C(0.5)) * C(0.5) * minmod<C>(fp - f0, f0 - fm);
-  }
-  return v;
+  return interp_combine<C>(f, b, ox, oy, oz);
 }
 
 }  // namespace dev

@@ -165,16 +165,16 @@ __device__ __forceinline__ const S* coarse_source(const SweepArgs& a, const Slot
 // (interp_value in lattice.hpp, with the parents' level table).  Only the
 // sweep variant for the interpolated explosion calls it, for the cells of a
 // lane whose source is special; the direction is a run-time argument and the
-// function is not inlined, which keeps that variant small.
+// function is not inlined, which keeps that variant small.  code and cz are
+// the block's table entries of x - e_A and x - 2 e_A, which the caller holds
+// in registers.
 template <typename S, int N>
 __device__ __noinline__ typename Form<S>::C coarse_value_rt(const S* cur, const S* prev, const S* par,
-                                                            const int32_t* nbr, const int32_t* par_nbr, int* err,
-                                                            int substep, int slot, int A, int i, int j, int k) {
+                                                            const int32_t* par_nbr, int* err, int substep, int slot,
+                                                            int A, int i, int j, int k, int code, int cz) {
   using C = typename Form<S>::C;
   constexpr int H = Geo<S, N>::H;
   const int EX = ex(A), EY = ey(A), EZ = ez(A);
-  const int32_t* tab = nbr + int64_t(slot) * 27;
-  auto sd = [](int c) { return c < 0 ? -1 : (c >= N ? 1 : 0); };
   auto parent = [&](int code, int lx, int ly, int lz, int aa) -> C {
     const int pp = kNbrCoarse0 - code;
     const int oc = pp & 7, pslot = pp >> 3;
@@ -183,7 +183,6 @@ __device__ __noinline__ typename Form<S>::C coarse_value_rt(const S* cur, const 
                               err);
   };
   const int sx = i - EX, sy = j - EY, sz = k - EZ;
-  const int code = tab[13 + sd(sx) + 3 * sd(sy) + 9 * sd(sz)];
   if (code == kNbrWall) return Form<S>::ld(cur + pdf_index<N>(opp(A), uint32_t(slot), uint32_t(i + N * (j + N * k))));
   if (code > kNbrCoarse0) {
     atomicOr(err, kErrNoSource);
@@ -191,7 +190,6 @@ __device__ __noinline__ typename Form<S>::C coarse_value_rt(const S* cur, const 
   }
   if (substep == 1) return parent(code, sx & (N - 1), sy & (N - 1), sz & (N - 1), A);
   const int zx = sx - EX, zy = sy - EY, zz = sz - EZ;
-  const int cz = tab[13 + sd(zx) + 3 * sd(zy) + 9 * sd(zz)];
   if (cz >= 0)
     return Form<S>::ld(prev + pdf_index<N>(A, uint32_t(cz), uint32_t((zx & (N - 1)) + N * ((zy & (N - 1)) + N * (zz & (N - 1))))));
   if (cz == kNbrWall) return parent(code, sx & (N - 1), sy & (N - 1), sz & (N - 1), opp(A));
@@ -202,10 +200,15 @@ __device__ __noinline__ typename Form<S>::C coarse_value_rt(const S* cur, const 
   return parent(cz, zx & (N - 1), zy & (N - 1), zz & (N - 1), A);
 }
 
-template <typename S, int N>
-__device__ __forceinline__ typename Form<S>::C coarse_value(const SweepArgs& a, int slot, int A, int i, int j, int k) {
+template <typename S, int N, int A>
+__device__ __forceinline__ typename Form<S>::C coarse_value(const SweepArgs& a, const SlotCache& sc, int slot, int i, int j,
+                                                           int k) {
+  constexpr int EX = ex(A), EY = ey(A), EZ = ez(A);
+  const int sx = i - EX, sy = j - EY, sz = k - EZ;
+  const int code = pick<-EX, -EY, -EZ>(sc, outside<N>(sx), outside<N>(sy), outside<N>(sz));
+  const int cz = pick<-EX, -EY, -EZ>(sc, outside<N>(sx - EX), outside<N>(sy - EY), outside<N>(sz - EZ));
   return coarse_value_rt<S, N>(static_cast<const S*>(a.cur), static_cast<const S*>(a.prev),
-                               static_cast<const S*>(a.par), a.nbr, a.par_nbr, a.err, a.substep, slot, A, i, j, k);
+                               static_cast<const S*>(a.par), a.par_nbr, a.err, a.substep, slot, A, i, j, k, code, cz);
 }
 
 // Coalescence (eq. ftoc): the value of a coalesced pair comes from the
@@ -370,7 +373,7 @@ __device__ __forceinline__ void fixups(const SweepArgs& a, const SlotCache& sc, 
     for (int c = 0; c < W; ++c)
       if ((spec >> c) & 1u)
         h[A][c] = (co >> c) & 1u ? C(Form<S>::ld(coalesced_source<S, N, A>(a, sc, i0 + c, j, k)))
-                                 : coarse_value<S, N>(a, slot, A, i0 + c, j, k);
+                                 : coarse_value<S, N, A>(a, sc, slot, i0 + c, j, k);
   } else if (spec) {
     C v[W];
 #pragma unroll
@@ -608,7 +611,7 @@ __device__ __forceinline__ void fixups_h8(const SweepArgs& a, const SlotCache& s
       if ((spec >> c) & 1u)
         set_half(q[A][c >> 1], c & 1,
                  (co >> c) & 1u ? Form<__half>::ld(coalesced_source<__half, N, A>(a, sc, i0 + c, j, k))
-                                : coarse_value<__half, N>(a, slot, A, i0 + c, j, k));
+                                : coarse_value<__half, N, A>(a, sc, slot, i0 + c, j, k));
   } else if (spec) {
     float v[8];
 #pragma unroll
