@@ -316,6 +316,7 @@ void emit(const lbm_forest* f, int L, int substep, std::vector<int>& r, const vo
     ia.refined = 1;
     ia.flags = d.flags;
     ia.par = parent_cur;
+    ia.par_face = parent_face;
     ia.save_in = f->save[q];
     ia.save_out = substep == 1 ? f->save[2] : f->save[q ^ 1];
     ia.err = f->d_err;

@@ -229,13 +229,19 @@ __device__ __forceinline__ void odd_store(const InplaceArgs& a, const SlotCache&
 // back-trace and the coarser level's coalescence need (inplace_save.hpp).
 
 // Post-collision value of the level-(L-1) parent of level-L cell (lx, ly, lz)
-// of the virtual block with coarse code `code` (homogeneous explosion).
+// of the virtual block with coarse code `code` (homogeneous explosion).  A
+// parent on the parent block's x face through which A leaves it is read
+// from the parent's x-face copy (as parent_ptr in the sweep does).
 template <typename S, int N, int A>
 __device__ __forceinline__ const S* iparent(const InplaceArgs& a, int code, int lx, int ly, int lz) {
   constexpr int H = N / 2;
   const int pp = kNbrCoarse0 - code;
   const int oc = pp & 7;
   const int px = (oc & 1 ? H : 0) + (lx >> 1), py = (oc & 2 ? H : 0) + (ly >> 1), pz = (oc & 4 ? H : 0) + (lz >> 1);
+  if constexpr (ex(A) != 0) {
+    if (px == (ex(A) > 0 ? N - 1 : 0))
+      return static_cast<const S*>(a.par_face) + xface_index<S, N, A>(uint32_t(pp >> 3), uint32_t(py + N * pz));
+  }
   return static_cast<const S*>(a.par) + pdf_index<N>(A, uint32_t(pp >> 3), uint32_t(px + N * (py + N * pz)));
 }
 
@@ -1009,7 +1015,7 @@ int64_t inplace_grid(int storage, int n, int64_t nblocks) {
 
 hipError_t launch_inplace(int storage, int n, const InplaceArgs& a, bool odd, hipStream_t stream) {
   if (!a.buf || !a.face || !a.entry || !a.nbr) return hipErrorInvalidValue;
-  if (a.refined && (!a.flags || !a.par || !a.save_in || !a.save_out || !a.err)) return hipErrorInvalidValue;
+  if (a.refined && (!a.flags || !a.par || !a.par_face || !a.save_in || !a.save_out || !a.err)) return hipErrorInvalidValue;
   switch (storage) {
     case 0: return dev::launch_inplace_t<double>(n, a, odd, stream);
     case 1: return dev::launch_inplace_t<float>(n, a, odd, stream);

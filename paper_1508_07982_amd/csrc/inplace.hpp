@@ -51,6 +51,7 @@ struct InplaceArgs {
   int32_t refined;
   const uint32_t* flags; // [slot] SlotFlags
   const void* par;       // level-(L-1) current state (two buffers): explosion source
+  const void* par_face;  // its x-face copy (parents on the parent block's x faces)
   const void* save_in;   // saves of the state at the start of the parent step (second substep reads)
   void* save_out;        // saves written: t + 1/2 (first substep), t + 1 (second substep)
   int* err;              // error bits (table lookup failures)

@@ -64,12 +64,13 @@ __host__ __device__ inline uint64_t pdf_at_rt(int a, uint64_t idx, uint64_t n3) 
 // Where a kernel reads or writes many of them, they are kept in an x-face
 // buffer instead: one element per (row, x direction, y, z), the 10
 // directions with a nonzero x component numbered in direction order.  The
-// (j, k) rows jk = j + n k come in groups of G = 32 bytes / element size
-// (4 in FP64, 8 in FP32, 16 in FP16: the rows of a 64-lane workgroup of the
-// sweep at n = 32), each group holding its rows for all 10 directions, so
-// that the face values one workgroup writes form one contiguous run of whole
-// 64-byte segments: element (row, q, jk) at 10 n^2 row + 10 G (jk / G) +
-// G q + jk mod G.
+// (j, k) rows jk = j + n k come in groups of G rows, each group holding its
+// rows for all 10 directions: element (row, q, jk) at 10 n^2 row +
+// 10 G (jk / G) + G q + jk mod G.  FP64 and FP32 take G = 32 bytes /
+// element size (4 and 8: the rows of a 64-lane workgroup of the sweep at
+// n = 32), so that the face values one workgroup writes form one contiguous
+// run of whole 64-byte segments; FP16 takes G = n^2 (one group per face,
+// direction after direction), which measured faster for its packed sweep.
 constexpr int kXDirs = 10;
 __host__ __device__ __forceinline__ constexpr int xdir_index(int a) {
   int q = 0;
@@ -85,22 +86,22 @@ __host__ __device__ __forceinline__ constexpr int xdir_dir(int q) {
   }
   return a;
 }
-// rows per group of the x-face layout for element type S
+// rows per group of the x-face layout for element type S and block size n
 template <typename S>
-__host__ __device__ constexpr int face_rows() {
-  return 32 / int(sizeof(S));
+__host__ __device__ constexpr int face_rows(int n) {
+  return sizeof(S) == 2 ? n * n : 32 / int(sizeof(S));
 }
 // element (row, q, jk): q the x-direction number
 template <typename S, int N>
 __host__ __device__ __forceinline__ uint64_t xface_at(uint64_t row, int q, uint32_t jk) {
-  constexpr uint32_t G = uint32_t(face_rows<S>());
+  constexpr uint32_t G = uint32_t(face_rows<S>(N));
   static_assert((N * N) % G == 0, "a whole number of row groups per face");
   return row * uint64_t(kXDirs * N * N) + uint64_t(jk / G) * (kXDirs * G) + uint64_t(q) * G + (jk % G);
 }
 // the inverse, for a block size known only at run time: element e -> (row, q, jk)
 template <typename S>
 __host__ __device__ __forceinline__ void xface_decode(int64_t e, int n, int64_t& row, int& q, int64_t& jk) {
-  constexpr int64_t G = face_rows<S>();
+  const int64_t G = face_rows<S>(n);
   const int64_t per = int64_t(kXDirs) * n * n, r = e % per;
   row = e / per;
   q = int((r % (kXDirs * G)) / G);
